@@ -1,0 +1,74 @@
+"""Seeded input generators: published SplitMix64 outputs, the C generator against a
+Python mirror, and the size/shape invariants of every synthetic workload."""
+import numpy as np
+
+import workloads as W
+
+
+def test_splitmix64_published_sequence():
+    # SplitMix64 seeded with 1234567: published first outputs of the reference generator
+    seq = [W.mix64((1234567 + k * W.GOLDEN64) & W.MASK64) for k in range(5)]
+    assert seq == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                   4593380528125082431, 16408922859458223821]
+    assert all(W.mix64(z) == W.mix64_py(z) for z in (0, 1, 2 ** 63, W.MASK64, 0xDEADBEEF))
+
+
+def test_modfilter_workload_matches_python_mirror():
+    off, vals = W.modfilter_workload(seed=1, n_parents=64, max_size=64)
+    b = W.mix64_py(1 ^ 0x5EED)
+    sizes = [W.mix64_py((b + p) & W.MASK64) % 65 for p in range(64)]
+    assert np.diff(off).tolist() == sizes
+    assert sizes[:8] == [22, 16, 13, 59, 64, 26, 36, 43]
+    base = W.mix64_py(1)
+    for p in (0, 5, 63):
+        exp = [W.mix64_py(base ^ ((p << 32) | i)) & 0xFFFFFFFF for i in range(sizes[p])]
+        assert vals[off[p]:off[p + 1]].tolist() == exp
+    full_off, _ = W.modfilter_workload()
+    assert len(full_off) == 4097 and np.diff(full_off).max() <= 64 and (np.diff(full_off) == 0).any()
+
+
+def test_hash_values_and_fixed_offsets():
+    v = W.hash_values(2, 8)
+    base = W.mix64_py(2)
+    assert v.tolist() == [W.mix64_py(base + i) & 0xFFFFFFFF for i in range(8)]
+    assert W.hash_values(2, 5, first=3).tolist() == v[3:8].tolist()
+    off = W.fixed_offsets(1 << 12, 64)
+    assert len(off) == 65 and off[-1] == 4096 and set(np.diff(off).tolist()) == {64}
+    off = W.fixed_offsets(10, 4)
+    assert off.tolist() == [0, 4, 8, 10]
+
+
+def test_text_workload_shape():
+    total = 1 << 20
+    text, starts, lengths = W.text_workload(seed=3, total_bytes=total)
+    assert len(text) == total and text[-1] == 10
+    ends = starts.astype(np.int64) + lengths
+    assert (text[ends] == 10).all()                          # every line ends with a newline
+    assert starts[0] == 0 and (starts[1:] == ends[:-1] + 1).all()
+    assert ends[-1] == total - 1
+    nl = np.zeros(total, bool)
+    nl[ends] = True
+    body = text[~nl]
+    assert ((body == 32) | ((body >= 97) & (body <= 122))).all()
+    assert abs((body == 32).mean() - 0.18) < 0.005
+    assert abs(lengths[:-1].mean() - 80) < 4 and lengths.max() <= 65536
+    assert (lengths == 0).any()
+
+
+def test_graph_workload_shape():
+    off, beta = W.graph_offsets(seed=4, n_vertices=1 << 16, n_edges=1 << 20, cap=100000)
+    deg = np.diff(off.astype(np.int64))
+    assert off[0] == 0 and off[-1] == 1 << 20 and (deg >= 0).all() and deg.max() <= 100000
+    assert (deg == 0).mean() > 0.2                          # many degree-0 vertices
+    assert deg.max() > 50 * deg.mean()                      # heavy tail
+    assert beta > 0
+
+
+def test_serving_shapes_and_streams():
+    n, m = W.stream_shapes(seed=5, n_streams=512)
+    assert ((n >= 1000) & (n <= 10 ** 7)).all() and ((m >= 1) & (m <= 4096)).all()
+    off, vals = W.serving_stream(5, 3, 5000, 7.5)
+    assert off[0] == 0 and off[-1] == 5000 and (np.diff(off.astype(np.int64)) >= 0).all()
+    assert len(vals) == 5000
+    t = W.arrivals(6, 100, 50.0)
+    assert (np.diff(t) > 0).all() and abs(t[-1] / 100 - 1 / 50.0) < 0.01
