@@ -1,0 +1,72 @@
+// Structures shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+namespace rs {
+
+// Device control block of a pipeline (one per pipeline, zero-initialised once).
+// The persistent kernel returns every counter to zero before it exits, so a launch
+// can be replayed (HIP graph) without any reset node.
+enum Ctl : uint32_t {
+    CTL_CLAIM = 0,     // next global claim index
+    CTL_DONE = 1,      // workgroups that have exited
+    CTL_ERROR = 2,     // watchdog / protocol error flag (sticky until read)
+    CTL_EPOCH = 3,     // launches completed (look-back state tags)
+    CTL_WORDS = 64
+};
+
+// Statistics slots per stream (u64 each).
+enum Stat : uint32_t {
+    ST_FIRINGS = 0,    // [3]
+    ST_ITEMS = 3,      // [3]
+    ST_FULL = 6,       // [3]
+    ST_SIGNALS = 9,    // [3]
+    ST_OUTPUTS = 12,
+    ST_WORDS = 16
+};
+
+// One stream of a batched launch (device work table entry).
+struct StreamDev {
+    const void *elements;
+    const uint32_t *offsets;       // CSR [P+1] or starts [P]
+    const uint32_t *lengths;       // nullptr for CSR
+    const uint32_t *pparam;        // per-parent context or nullptr
+    uint32_t *agg_count;
+    unsigned long long *agg_sum;
+    uint32_t *agg_min;
+    uint32_t *agg_max;
+    uint32_t *out_items;           // ordered output stream or nullptr
+    unsigned long long *lookback;  // per-claim look-back words (emit_outputs) or nullptr
+    unsigned long long *stats;     // ST_WORDS counters or nullptr
+    uint32_t n_parents;
+    uint32_t n_elements;
+    uint32_t parents_per_claim;    // B
+    uint32_t n_claims;
+    uint32_t claim_begin;          // first global claim index of this stream
+    uint32_t pad[3];
+};
+
+struct LaunchArgs {
+    const StreamDev *streams;
+    uint32_t *ctl;
+    const void *dummy;             // 16 readable bytes: source of ring lanes past a stream's end
+    uint32_t n_streams;
+    uint32_t total_claims;
+    uint32_t param[4];
+    uint32_t agg_fields;
+    uint32_t collect_stats;
+    uint32_t emit_outputs;
+    uint32_t pad;
+};
+
+// Kernel entry points (defined in rs_kernels.hip).
+// Most parents one claim may hold for ensemble width w.
+inline uint32_t claim_parents_max(uint32_t w) { return w; }
+bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width);
+int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a,
+                    uint32_t grid, void *stream);
+int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width);
+// 0 if the regions are well formed, 1 + first bad parent otherwise, -hipError on failure.
+int validate_device_regions(const uint32_t *offs, const uint32_t *lens, uint32_t P, uint32_t n, void *stream);
+
+}  // namespace rs

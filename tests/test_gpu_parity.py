@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path through the C ABI against the serial oracle, element by
+element, on seeded inputs (integer results: bit-exact)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_2006_07478_amd as rs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+STRATS = [rs.RS_TAG, rs.RS_SIGNAL]
+SNAME = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal"}
+ALL = rs.RS_COUNT | rs.RS_SUM | rs.RS_MIN | rs.RS_MAX
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check(got, ref, fields=("count", "sum", "min", "max"), where=""):
+    for f in fields:
+        g, r = got[f], getattr(ref, f)
+        if not np.array_equal(g, r):
+            bad = np.nonzero(g != r)[0]
+            raise AssertionError(f"{where}: field {f} differs at {len(bad)} parents, first {bad[:5].tolist()}: "
+                                 f"gpu {g[bad[:5]].tolist()} oracle {r[bad[:5]].tolist()}")
+
+
+def run_one(kind, strategy, width, offsets, elements, lengths=None, parent_param=None, param=(0, 0, 0, 0),
+            fields=ALL, device=False, flags=0):
+    import torch
+    with rs.Pipeline(kind, strategy=strategy, ensemble_width=width, agg_fields=fields, param=param,
+                     flags=flags) as p:
+        if device:
+            to = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a).view(
+                np.int32 if a.dtype == np.uint32 else np.uint8)).cuda()
+            sid = p.push(to(offsets), to(elements), lengths=to(lengths), parent_param=to(parent_param),
+                         n_elements=len(elements))
+        else:
+            sid = p.push(offsets, elements, lengths=lengths, parent_param=parent_param)
+        p.run()
+        out = p.read(sid)
+        st = p.stats(sid) if flags & rs.RS_COLLECT_STATS else None
+    return out, st
+
+
+# ---- hand-worked streams ----
+
+@pytest.mark.parametrize("name", ["e1_modfilter.json", "e2_hash_expand.json", "e3_text_words.json",
+                                  "e4_graph_thresh.json"])
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("width", [64, 256])
+def test_golden_streams(name, strategy, width):
+    g = json.load(open(os.path.join(GOLDEN, name)))
+    say("golden", name, SNAME[strategy], width)
+    kind = g["kind"]
+    if kind == rs.RS_TEXT_WORDS:
+        elems = np.frombuffer(g["text"].encode(), np.uint8)
+        got, _ = run_one(kind, strategy, width, np.array(g["starts"], np.uint32), elems,
+                         lengths=np.array(g["lengths"], np.uint32))
+    else:
+        got, _ = run_one(kind, strategy, width, np.array(g["offsets"], np.uint32), np.array(g["elements"], np.uint32),
+                         parent_param=np.array(g["thresholds"], np.uint32) if "thresholds" in g else None,
+                         param=tuple(g.get("param", (0, 0, 0, 0))))
+    for f in ("count", "sum", "min", "max"):
+        assert [int(v) for v in got[f]] == g["expected"][f], f
+
+
+# ---- sum app, 4096 parents with sizes in [0, 64] ----
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("width", [64, 128, 256, 512])
+@pytest.mark.parametrize("device", [False, True])
+def test_sum_app_4096_parents(strategy, width, device):
+    say("sum app", SNAME[strategy], width, "device" if device else "host")
+    offsets, vals = workloads.modfilter_workload(seed=1, n_parents=4096, max_size=64)
+    ref = oracle.run(oracle.MODFILTER, offsets, vals, param=(4, 0, 0, 0))
+    got, _ = run_one(rs.RS_MODFILTER, strategy, width, offsets, vals, param=(4, 0, 0, 0),
+                     fields=rs.RS_COUNT | rs.RS_SUM, device=device)
+    check(got, ref, ("count", "sum"), "sum app")
+
+
+@pytest.mark.parametrize("modulus,residue", [(1, 0), (7, 3), (4, 2)])
+def test_modfilter_parameters(modulus, residue):
+    offsets, vals = workloads.modfilter_workload(seed=17, n_parents=3000, max_size=90)
+    ref = oracle.run(oracle.MODFILTER, offsets, vals, param=(modulus, residue, 0, 0))
+    for strategy in STRATS:
+        got, _ = run_one(rs.RS_MODFILTER, strategy, 256, offsets, vals, param=(modulus, residue, 0, 0))
+        check(got, ref, where=f"mod {modulus} {residue}")
+
+
+# ---- boundary-frequency sweep, reduced size: several tiles and a ragged tail ----
+
+@pytest.mark.parametrize("L", [1, 4, 16, 64, 256, 1024, 4096])
+@pytest.mark.parametrize("strategy", STRATS)
+def test_hash_expand_fixed_L(L, strategy):
+    n = (1 << 18) + 13                     # not a multiple of the region length or of 4
+    say("hash/expand L", L, SNAME[strategy])
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    got, _ = run_one(rs.RS_HASH_EXPAND, strategy, 256, offsets, vals)
+    check(got, ref, where=f"L={L}")
+
+
+@pytest.mark.parametrize("width", [64, 128, 512])
+@pytest.mark.parametrize("strategy", STRATS)
+def test_hash_expand_widths_variable_regions(width, strategy):
+    say("hash/expand width", width, SNAME[strategy])
+    offsets = workloads.uniform_offsets(5, 3000, 300)
+    vals = workloads.hash_values(5, int(offsets[-1]))
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    got, _ = run_one(rs.RS_HASH_EXPAND, strategy, width, offsets, vals)
+    check(got, ref, where=f"width {width}")
+
+
+# ---- edge cases ----
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_edge_cases(strategy):
+    say("edge cases", SNAME[strategy])
+    # all parents empty
+    offs = np.zeros(1001, np.uint32)
+    got, _ = run_one(rs.RS_HASH_EXPAND, strategy, 256, offs, np.zeros(4, np.uint32))
+    assert (got["count"] == 0).all() and (got["min"] == 0xFFFFFFFF).all() and (got["max"] == 0).all()
+    # one parent holds the whole stream
+    vals = workloads.hash_values(3, 200003)
+    offs = np.array([0, 200003], np.uint32)
+    ref = oracle.run(oracle.HASH_EXPAND, offs, vals)
+    got, _ = run_one(rs.RS_HASH_EXPAND, strategy, 256, offs, vals)
+    check(got, ref, where="one parent")
+    # a single element 0 under the mod filter
+    got, _ = run_one(rs.RS_MODFILTER, strategy, 64, np.array([0, 1], np.uint32), np.array([0], np.uint32),
+                     fields=rs.RS_COUNT | rs.RS_SUM)
+    assert int(got["count"][0]) == 1 and int(got["sum"][0]) == 0
+    # regions that do not start at element 0 and skip elements at the end
+    vals = workloads.hash_values(4, 5000)
+    offs = np.array([7, 7, 100, 2500, 4990], np.uint32)
+    ref = oracle.run(oracle.HASH_EXPAND, offs, vals)
+    got, _ = run_one(rs.RS_HASH_EXPAND, strategy, 128, offs, vals)
+    check(got, ref, where="offset start")
+
+
+def test_zero_parents():
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256) as p:
+        sid = p.push(np.zeros(1, np.uint32), np.zeros(4, np.uint32))
+        p.run()
+        got = p.read(sid)
+        assert all(len(v) == 0 for v in got.values())
+
+
+# ---- text and graph kinds ----
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("width", [64, 256])
+def test_text_words(strategy, width):
+    say("text", SNAME[strategy], width)
+    text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 20)
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths)
+    got, _ = run_one(rs.RS_TEXT_WORDS, strategy, width, starts, text, lengths=lengths)
+    check(got, ref, where="text")
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_text_long_lines_and_long_words(strategy):
+    say("text long", SNAME[strategy])
+    text, starts, lengths = workloads.text_workload(seed=8, total_bytes=1 << 20, mean_len=3000.0, max_len=65536,
+                                                    space_per_65536=300)
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths)
+    got, _ = run_one(rs.RS_TEXT_WORDS, strategy, 256, starts, text, lengths=lengths)
+    check(got, ref, where="text long")
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("width", [64, 256])
+def test_graph_threshold(strategy, width):
+    say("graph", SNAME[strategy], width)
+    offsets, w, thr, _ = workloads.graph_workload(seed=4, n_vertices=1 << 14, n_edges=1 << 18, cap=20000)
+    ref = oracle.run(oracle.GRAPH_THRESH, offsets, w, parent_param=thr)
+    got, _ = run_one(rs.RS_GRAPH_THRESH, strategy, width, offsets, w, parent_param=thr)
+    check(got, ref, where="graph")
+
+
+# ---- batching, replay, statistics ----
+
+def test_batched_streams_equal_alone():
+    say("batched")
+    shapes = [(5000, 1.0), (20000, 37.5), (100000, 700.0), (3000, 4096.0), (1, 1.0), (77777, 3.0)]
+    streams = [workloads.serving_stream(5, s, n, m) for s, (n, m) in enumerate(shapes)]
+    for strategy in STRATS:
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:
+            ids = [p.push(o, v) for o, v in streams]
+            p.run()
+            for sid, (o, v) in zip(ids, streams):
+                check(p.read(sid), oracle.run(oracle.HASH_EXPAND, o, v), where="batched")
+
+
+def test_run_again_replays_bit_exact():
+    offsets = workloads.fixed_offsets(1 << 20, 64)
+    vals = workloads.hash_values(2, 1 << 20)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    for strategy in STRATS:
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:
+            sid = p.push(offsets, vals)
+            p.run()
+            for _ in range(4):
+                p.run_again()
+                check(p.read(sid), ref, where="replay")
+
+
+def test_signal_occupancy_matches_closed_form():
+    """Enumerating-node firings at fixed L: ceil(L/w) per region, L/(w ceil(L/w)) occupancy."""
+    w = 256
+    for L in (1, 100, 256, 300, 4096):
+        n = L * 512
+        offsets = workloads.fixed_offsets(n, L)
+        vals = workloads.hash_values(2, n)
+        _, st = run_one(rs.RS_HASH_EXPAND, rs.RS_SIGNAL, w, offsets, vals, flags=rs.RS_COLLECT_STATS)
+        fires = 512 * -(-L // w)
+        assert st.firings[0] == fires and st.items[0] == n
+        assert st.signals[0] == 512 and st.signals[2] == 512
+        assert st.full[0] == 512 * (L // w)
+        _, st_t = run_one(rs.RS_HASH_EXPAND, rs.RS_TAG, w, offsets, vals, flags=rs.RS_COLLECT_STATS)
+        assert st_t.items[0] == n and st_t.signals[0] == 0
