@@ -213,6 +213,45 @@ int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out);
  * RS_ESTATE (still running). */
 int stream_release(rs_pipeline *p, uint64_t stream_id);
 
+/* One request of the serving loop: its input stream and when it arrives, in seconds after
+ * serve() starts. */
+typedef struct {
+    double arrival_s;
+    rs_stream_desc stream;
+} rs_request;
+
+/* Host clock of one request, in seconds after serve() starts: arrival, push (input copied and
+ * registered), launch (its batch enqueued) and completion (its aggregates read back). */
+typedef struct {
+    double arrival_s;
+    double pushed_s;
+    double launched_s;
+    double completed_s;
+    uint64_t batch;           /* launch batch the request ran in */
+    int32_t status;           /* RS_OK or the error of this request */
+    uint32_t pad;
+} rs_request_timing;
+
+/* Serve a sequence of requests in real time (continuous batching).  The loop pushes every
+ * request whose arrival time has passed, admits pushed requests into a new batch whenever
+ * one of the pipeline's two launch lanes is free and the HBM budget allows (requests that
+ * do not fit wait for earlier ones to finish and release their memory), reaps finished
+ * batches without blocking, copies each request's aggregates into out[i] (host memory;
+ * out may be NULL, or out[i] fields NULL) and releases it.  With RS_RUN_PER_STREAM every
+ * request is launched alone, in arrival order, on one lane: the one-launch-per-stream
+ * baseline.  Requests are sorted by arrival by the caller.  timing[i] receives the
+ * request's clock.  Returns RS_OK when every request completed; a request that fails
+ * records its error in timing[i].status and the loop goes on.
+ * Errors: RS_EINVAL (NULL arguments, unsorted arrivals). */
+int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view *out, rs_request_timing *timing,
+          uint32_t flags);
+
+/* Measurement aid: copy `bytes` (a multiple of 16) from src to dst, both 16-byte aligned device
+ * memory, with a plain grid-stride copy kernel enqueued on hip_stream (NULL: the default stream).
+ * It is the achievable-bandwidth reference beside the pipeline kernels and the known-size copy
+ * that calibrates hardware traffic counters.  Errors: RS_EINVAL, RS_EDEVICE. */
+int hbm_probe(const void *src, void *dst, uint64_t bytes, void *hip_stream);
+
 /* Wait for outstanding work and free everything the pipeline owns.  Borrowed memory is
  * untouched. */
 int pipeline_destroy(rs_pipeline *p);

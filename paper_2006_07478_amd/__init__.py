@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "RS_OK", -1: "RS_EINVAL", -2: "RS_ENOMEM", -3: "RS_EDEVICE", 
                 -5: "RS_ENOTREADY", -6: "RS_ESTATE", -7: "RS_ENOTFOUND"}
 
 ABI_FUNCTIONS = ["pipeline_create", "pipeline_set_stream", "stream_push", "run", "run_again",
-                 "read_aggregates", "read_outputs", "rs_stats", "stream_release", "pipeline_destroy",
+                 "read_aggregates", "read_outputs", "rs_stats", "stream_release", "serve", "hbm_probe", "pipeline_destroy",
                  "rs_last_error"]
 
 
@@ -63,6 +63,16 @@ class rs_stats_t(ctypes.Structure):
                 ("n_outputs", ctypes.c_uint64)]
 
 
+class rs_request(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("stream", rs_stream_desc)]
+
+
+class rs_request_timing(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("pushed_s", ctypes.c_double), ("launched_s", ctypes.c_double),
+                ("completed_s", ctypes.c_double), ("batch", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_uint32)]
+
+
 _lib = None
 
 
@@ -83,7 +93,10 @@ def lib():
         L.read_outputs.argtypes = [vp, u64, vp, u64, ctypes.POINTER(u64), u32]
         L.rs_stats.argtypes = [vp, u64, ctypes.POINTER(rs_stats_t)]
         L.stream_release.argtypes = [vp, u64]
+        L.serve.argtypes = [vp, ctypes.POINTER(rs_request), u64, ctypes.POINTER(rs_agg_view),
+                            ctypes.POINTER(rs_request_timing), u32]
         L.pipeline_destroy.argtypes = [vp]
+        L.hbm_probe.argtypes = [vp, vp, u64, vp]
         L.rs_last_error.restype = ctypes.c_char_p
         L.rs_last_error.argtypes = []
         for name in ABI_FUNCTIONS[:-1]:
@@ -146,6 +159,14 @@ def rs_stats(p, stream_id):
 
 def stream_release(p, stream_id):
     return _check(lib().stream_release(p, stream_id))
+
+
+def serve(p, reqs, n, out, timing, flags=0):
+    return _check(lib().serve(p, reqs, n, out, timing, flags))
+
+
+def hbm_probe(src_ptr, dst_ptr, nbytes, hip_stream=None):
+    return _check(lib().hbm_probe(src_ptr, dst_ptr, nbytes, hip_stream))
 
 
 def pipeline_destroy(p):
@@ -212,8 +233,7 @@ class Pipeline:
     def set_stream(self, hip_stream_ptr):
         pipeline_set_stream(self.h, hip_stream_ptr)
 
-    def push(self, offsets, elements, lengths=None, parent_param=None, n_elements=None):
-        """Push one stream.  numpy inputs are copied (RS_MEM_HOST); torch tensors are borrowed."""
+    def _desc(self, offsets, elements, lengths=None, parent_param=None, n_elements=None):
         dev = not isinstance(elements, np.ndarray)
         s = rs_stream_desc()
         s.mem = RS_MEM_DEVICE if dev else RS_MEM_HOST
@@ -234,6 +254,11 @@ class Pipeline:
             ptr, k = _ptr(arr)
             keep.append(k)
             setattr(s, name, ptr)
+        return s, keep, dev
+
+    def push(self, offsets, elements, lengths=None, parent_param=None, n_elements=None):
+        """Push one stream.  numpy inputs are copied (RS_MEM_HOST); torch tensors are borrowed."""
+        s, keep, dev = self._desc(offsets, elements, lengths, parent_param, n_elements)
         sid = stream_push(self.h, s)
         if dev:
             self._keep[sid] = keep          # borrowed device memory must outlive the stream
@@ -259,8 +284,46 @@ class Pipeline:
         read_aggregates(self.h, sid, v, flags)
         return {k: a[:P] for k, a in out.items()}
 
+    def outputs(self, sid, flags=RS_READ_BLOCK):
+        """The ordered surviving-item stream of a stream (pipelines with emit_outputs)."""
+        n = read_outputs(self.h, sid, None, 0, flags)
+        out = np.zeros(max(n, 1), np.uint32)
+        read_outputs(self.h, sid, out.ctypes.data, n, flags)
+        return out[:n]
+
     def stats(self, sid):
         return rs_stats(self.h, sid)
+
+    def serve(self, requests, arrivals, per_stream=False, read=True):
+        """Run the native serving loop over requests = [(offsets, elements[, lengths, parent_param])]
+        arriving at the given times (seconds, sorted).  Returns (results, timings): results[i] is a
+        dict of aggregate arrays (or None when read is False) and timings a list of dicts."""
+        n = len(requests)
+        reqs = (rs_request * max(n, 1))()
+        outs = (rs_agg_view * max(n, 1))()
+        tim = (rs_request_timing * max(n, 1))()
+        keep, results = [], []
+        for i, r in enumerate(requests):
+            r = tuple(r) + (None,) * (4 - len(r))
+            s, k, _ = self._desc(r[0], r[1], r[2], r[3])
+            keep.append(k)
+            reqs[i].arrival_s = float(arrivals[i])
+            reqs[i].stream = s
+            P = int(s.n_parents)
+            res = None
+            if read:
+                res = {}
+                for name, bit, dt in FIELDS:
+                    if self.desc.agg_fields & bit:
+                        a = np.zeros(max(P, 1), dt)
+                        res[name] = a
+                        setattr(outs[i], name, a.ctypes.data)
+            results.append((res, P))
+        serve(self.h, reqs, n, outs if read else None, tim, RS_RUN_PER_STREAM if per_stream else 0)
+        out = [None if res is None else {k: a[:P] for k, a in res.items()} for res, P in results]
+        timings = [dict(arrival=t.arrival_s, pushed=t.pushed_s, launched=t.launched_s, completed=t.completed_s,
+                        batch=t.batch, status=t.status) for t in tim[:n]]
+        return out, timings
 
     def release(self, sid):
         stream_release(self.h, sid)

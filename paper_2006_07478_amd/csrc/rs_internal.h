@@ -22,6 +22,7 @@ enum Stat : uint32_t {
     ST_FULL = 6,       // [3]
     ST_SIGNALS = 9,    // [3]
     ST_OUTPUTS = 12,
+    ST_ERROR = 15,     // low word: nonzero when a claim found malformed regions
     ST_WORDS = 16
 };
 
@@ -60,13 +61,15 @@ struct LaunchArgs {
 };
 
 // Kernel entry points (defined in rs_kernels.hip).
-// Most parents one claim may hold for ensemble width w.
-inline uint32_t claim_parents_max(uint32_t w) { return w; }
+// Lanes per workgroup of the kernel for ensemble width w (w = lanes * items per lane).
+uint32_t lanes_of(uint32_t ensemble_width);
+// Most parents one claim may hold: one region-table entry per lane, plus the end offset.
+inline uint32_t claim_parents_max(uint32_t ensemble_width) { return lanes_of(ensemble_width) - 1u; }
 bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width);
 int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a,
                     uint32_t grid, void *stream);
 int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width);
-// 0 if the regions are well formed, 1 + first bad parent otherwise, -hipError on failure.
-int validate_device_regions(const uint32_t *offs, const uint32_t *lens, uint32_t P, uint32_t n, void *stream);
+int launch_probe_copy(const void *src, void *dst, unsigned long long bytes, uint32_t n_cu, void *stream);
+
 
 }  // namespace rs

@@ -5,16 +5,19 @@
 // node A) with a non-preemptive scheduler, and it competes with every other
 // workgroup for parent batches ("claims") through a device atomic on a common
 // counter, returning only when every claim of every stream in the launch is done.
-// A firing of a node consumes an ensemble of at most W items, one per lane.
+// A firing of a node consumes an ensemble of at most w = W*V items: item i of the
+// ensemble sits on lane i mod W, in round i / W, so one firing is V rounds of
+// W-wide SIMD work.
 //
 // Nodes are joined by fixed-size LDS queues.  Data-dependent output counts are
 // compacted with wave64 ballot/mbcnt ranks plus an LDS prefix over the waves.
 // Region boundaries travel either
-//   - as signals (RS_SIGNAL): an end-of-region slot sits in the queue at its exact
-//     stream position; the items between two slots are that signal's credit (the
-//     in-band form of the credit protocol of §3.1), a consumer's ensemble never
-//     extends past the next slot (the SIMD rule of §3.3), and a node consumes a
-//     slot only when no item precedes it, running end() for that region; or
+//   - as signals (RS_SIGNAL): an end-of-region slot sits in the data queue at its
+//     exact stream position and a small signal queue records where the slots are;
+//     the items between two slots are that signal's credit (the in-band form of the
+//     credit protocol of §3.1), a consumer's ensemble never extends past the next
+//     slot (the SIMD rule of §3.3), and a node consumes a slot only when no item
+//     precedes it, running end() for that region; or
 //   - as tags (RS_TAG): every queued item carries its region index, ensembles mix
 //     regions freely, and the aggregating node reduces by tag (§5).
 // Aggregates are exact integer reductions kept in LDS slots per claim and written
@@ -23,8 +26,9 @@
 //
 // Elements reach the enumerating node through an LDS ring filled by direct
 // global->LDS loads (global_load_lds_dwordx4), NS chunks deep, independent of
-// where ensembles or regions begin.  The compiler does not track which chunk a
-// read touches, so the ring is read with inline-asm ds_read and completion is
+// where ensembles or regions begin; the next claim's region table is loaded into
+// registers while the current claim runs.  The compiler does not track which chunk
+// a read touches, so the ring is read with inline-asm ds_read and completion is
 // managed with explicit vmcnt waits and a barrier that does not drain vmcnt.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -47,7 +51,7 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
 }
 
 // Salt s of the stage hash: H(x, s) = fmix32(x ^ (0x9E3779B9 * (s + 1))).
-__device__ __forceinline__ uint32_t salt_key(uint32_t s) { return 0x9E3779B9u * (s + 1u); }
+__device__ __forceinline__ constexpr uint32_t salt_key(uint32_t s) { return 0x9E3779B9u * (s + 1u); }
 
 // ---------------------------------------------------------------- wave / workgroup helpers
 
@@ -59,9 +63,7 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
 
 // Workgroup barrier that waits for this wave's LDS operations only (not for
 // outstanding global->LDS chunk loads, whose completion is waited for explicitly).
-__device__ __forceinline__ void bar() {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
+__device__ __forceinline__ void bar() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Wait until at most N vector-memory operations of this wave are outstanding.
 template <int N>
@@ -96,6 +98,27 @@ __device__ __forceinline__ uint32_t ring_u32(uint32_t addr) {
     asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr) : "memory");
     return v;
 }
+__device__ __forceinline__ void ring_u32x4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t &v0,
+                                           uint32_t &v1, uint32_t &v2, uint32_t &v3) {
+    asm volatile(
+        "ds_read_b32 %0, %4\n\t"
+        "ds_read_b32 %1, %5\n\t"
+        "ds_read_b32 %2, %6\n\t"
+        "ds_read_b32 %3, %7\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
+        : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+        : "memory");
+}
+__device__ __forceinline__ void ring_u32x2(uint32_t a0, uint32_t a1, uint32_t &v0, uint32_t &v1) {
+    asm volatile(
+        "ds_read_b32 %0, %2\n\t"
+        "ds_read_b32 %1, %3\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v0), "=&v"(v1)
+        : "v"(a0), "v"(a1)
+        : "memory");
+}
 __device__ __forceinline__ uint32_t ring_u8(uint32_t addr) {
     uint32_t v;
     asm volatile("ds_read_u8 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr) : "memory");
@@ -105,29 +128,67 @@ __device__ __forceinline__ void ring_w8(uint32_t addr, uint32_t v) {
     asm volatile("ds_write_b8 %0, %1\n\ts_waitcnt lgkmcnt(0)" : : "v"(addr), "v"(v) : "memory");
 }
 
-// Exclusive prefix of small per-lane counts n in [0, 3] over the workgroup.
-template <int W>
-__device__ __forceinline__ uint32_t wg_scan3(uint32_t n, uint32_t *scr, uint32_t &total) {
-    const uint64_t b0 = __ballot(n & 1u);
-    const uint64_t b1 = __ballot((n >> 1) & 1u);
-    const uint32_t within = rank_below(b0) + 2u * rank_below(b1);
-    const uint32_t wsum = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1);
-    if constexpr (W == 64) {
-        total = uni(wsum);
-        return within;
+// V u32 ring words at the given LDS addresses, issued together, waited for once.
+template <int V>
+__device__ __forceinline__ void ring_read(const uint32_t (&addr)[V], uint32_t (&out)[V]) {
+    if constexpr (V == 4) {
+        ring_u32x4(addr[0], addr[1], addr[2], addr[3], out[0], out[1], out[2], out[3]);
+    } else if constexpr (V == 2) {
+        ring_u32x2(addr[0], addr[1], out[0], out[1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) out[k] = ring_u32(addr[k]);
+    }
+}
+
+// Exclusive prefix of per-item counts n[k] (0..3) over an ensemble laid out as item
+// k*W + lane, in that order.  off[k] is the item's first output slot relative to the
+// firing's base; total is the firing's output count (uniform).
+template <int W, int V, bool TWO_BITS>
+__device__ __forceinline__ void ens_scan(const uint32_t (&n)[V], uint32_t (&off)[V], uint32_t &total,
+                                         uint32_t *scr) {
+    constexpr uint32_t NW = W / 64;
+    uint32_t within[V], wsum[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const uint64_t b0 = __ballot(n[k] & 1u);
+        within[k] = rank_below(b0);
+        wsum[k] = (uint32_t)__popcll(b0);
+        if constexpr (TWO_BITS) {
+            const uint64_t b1 = __ballot((n[k] >> 1) & 1u);
+            within[k] += 2u * rank_below(b1);
+            wsum[k] += 2u * (uint32_t)__popcll(b1);
+        }
+    }
+    if constexpr (NW == 1) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            off[k] = run + within[k];
+            run += wsum[k];
+        }
+        total = uni(run);
     } else {
         const uint32_t wv = threadIdx.x >> 6;
-        if ((threadIdx.x & 63u) == 0) scr[wv] = wsum;
-        bar();
-        uint32_t before = 0, all = 0;
+        if ((threadIdx.x & 63u) == 0) {
 #pragma unroll
-        for (uint32_t i = 0; i < (uint32_t)W / 64u; ++i) {
-            const uint32_t s = scr[i];
-            before += (i < wv) ? s : 0u;
-            all += s;
+            for (int k = 0; k < V; ++k) scr[k * NW + wv] = wsum[k];
         }
-        total = uni(all);
-        return before + within;
+        bar();
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            uint32_t before = 0, all = 0;
+#pragma unroll
+            for (uint32_t w = 0; w < NW; ++w) {
+                const uint32_t s = scr[k * NW + w];
+                before += (w < wv) ? s : 0u;
+                all += s;
+            }
+            off[k] = run + before + within[k];
+            run += all;
+        }
+        total = uni(run);
     }
 }
 
@@ -198,21 +259,21 @@ __device__ __forceinline__ Acc wg_reduce(Acc a, uint32_t *scr) {
         constexpr uint32_t NW = W / 64;
         const uint32_t wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63u) == 0) {
-            scr[16 + wv] = a.cnt;
-            scr[32 + 2 * wv] = (uint32_t)a.sum;
-            scr[33 + 2 * wv] = (uint32_t)(a.sum >> 32);
-            scr[64 + wv] = a.mn;
-            scr[80 + wv] = a.mx;
+            scr[64 + wv] = a.cnt;
+            scr[80 + 2 * wv] = (uint32_t)a.sum;
+            scr[81 + 2 * wv] = (uint32_t)(a.sum >> 32);
+            scr[112 + wv] = a.mn;
+            scr[128 + wv] = a.mx;
         }
         bar();
         Acc r;
         acc_reset(r);
 #pragma unroll
         for (uint32_t i = 0; i < NW; ++i) {
-            r.cnt += scr[16 + i];
-            r.sum += (unsigned long long)scr[32 + 2 * i] | ((unsigned long long)scr[33 + 2 * i] << 32);
-            r.mn = r.mn < scr[64 + i] ? r.mn : scr[64 + i];
-            r.mx = r.mx > scr[80 + i] ? r.mx : scr[80 + i];
+            r.cnt += scr[64 + i];
+            r.sum += (unsigned long long)scr[80 + 2 * i] | ((unsigned long long)scr[81 + 2 * i] << 32);
+            r.mn = r.mn < scr[112 + i] ? r.mn : scr[112 + i];
+            r.mx = r.mx > scr[128 + i] ? r.mx : scr[128 + i];
         }
         return r;
     }
@@ -220,46 +281,58 @@ __device__ __forceinline__ Acc wg_reduce(Acc a, uint32_t *scr) {
 
 // ---------------------------------------------------------------- geometry
 
-template <int W>
+template <int W, int V, bool HAS_E>
 struct Geo {
-    static constexpr uint32_t BMAX = W;          // parents in one claim, at most
-    static constexpr uint32_t D1 = 2 * W;        // slots of the queue in front of the second node
-    static constexpr uint32_t D2 = 4 * W;        // slots of the queue in front of the third node
+    static constexpr uint32_t EW = W * V;        // ensemble width: items one firing consumes
+    static constexpr uint32_t BMAX = W - 1;      // parents in one claim, at most (B+1 offsets, one per lane)
+    static constexpr uint32_t D1 = 2 * EW;       // data slots in front of the second node
+    static constexpr uint32_t D2 = HAS_E ? 4 * EW : 1;   // in front of the third node (k = 3 expansion)
+    static constexpr uint32_t SQ = 256;          // signal queue capacity (finite S of §3.1)
     static constexpr uint32_t CHB = 16 * W;      // bytes of one ring chunk: one 16-byte load per lane
     static constexpr uint32_t NS = 4;            // chunks in the element ring
     static constexpr uint32_t RING = NS * CHB;
 };
 
-enum Misc : uint32_t { M_NEXT = 100, M_JLAST = 101, M_PARTIAL = 102 };
+enum Misc : uint32_t {
+    M_NEXT = 200, M_JLAST = 201, M_BASE_LO = 202, M_BASE_HI = 203, M_BAD = 204, M_WORDS = 208
+};
+
+// Region table of one claim, as loaded from HBM by one lane (lane t holds parent p0 + t).
+struct ClaimRegs {
+    uint32_t off;      // CSR offsets[p0 + t] (t <= nb), or start of region p0 + t (t < nb)
+    uint32_t len;      // length of region p0 + t (start+length streams)
+    uint32_t ctx;      // per-parent context
+};
 
 // ---------------------------------------------------------------- the pipeline kernel
 
-template <int KIND, int STRAT, int W>
+template <int KIND, int STRAT, int W, int V>
 __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
-    using G = Geo<W>;
     constexpr bool TAG = (STRAT == RS_TAG);
     constexpr bool HAS_E = (KIND == RS_HASH_EXPAND || KIND == RS_TEXT_WORDS);
     constexpr bool BYTES = (KIND == RS_TEXT_WORDS);
     constexpr bool CTXP = (KIND == RS_GRAPH_THRESH);
-    constexpr uint32_t EB = BYTES ? 1u : 4u;          // element bytes
-    constexpr uint32_t KE = (KIND == RS_HASH_EXPAND) ? 3u : 1u;   // outputs per input of E
+    constexpr uint32_t EB = BYTES ? 1u : 4u;                       // element bytes
+    constexpr uint32_t KE = (KIND == RS_HASH_EXPAND) ? 3u : 1u;    // outputs per input of E
+    using G = Geo<W, V, HAS_E>;
+    constexpr uint32_t EW = G::EW;
 
     __shared__ __attribute__((aligned(16))) uint8_t ring[G::RING];
-    __shared__ uint32_t V[G::BMAX + 1];
-    __shared__ uint32_t SX[BYTES ? G::BMAX : 1];
-    __shared__ uint32_t CX[CTXP ? G::BMAX : 1];
+    __shared__ uint32_t VT[G::BMAX + 1];             // region starts in enumeration order, end at [nb]
+    __shared__ uint32_t SX[BYTES ? G::BMAX : 1];     // region start addresses (start+length streams)
+    __shared__ uint32_t CX[CTXP ? G::BMAX : 1];      // per-parent context
     __shared__ uint32_t s_cnt[G::BMAX];
     __shared__ unsigned long long s_sum[G::BMAX];
     __shared__ uint32_t s_min[G::BMAX];
     __shared__ uint32_t s_max[G::BMAX];
     __shared__ uint32_t q1v[G::D1];
-    __shared__ uint32_t q1a[KIND == RS_HASH_EXPAND ? G::D1 : 1];
-    __shared__ uint32_t q1t[TAG ? G::D1 : 1];
-    __shared__ uint32_t sp1[TAG ? 1 : G::D1];
-    __shared__ uint32_t q2v[HAS_E ? G::D2 : 1];
-    __shared__ uint32_t q2t[(HAS_E && TAG) ? G::D2 : 1];
-    __shared__ uint32_t sp2[(HAS_E && !TAG) ? G::D2 : 1];
-    __shared__ uint32_t misc[128];
+    __shared__ uint8_t q1a[KIND == RS_HASH_EXPAND ? G::D1 : 1];
+    __shared__ uint16_t q1t[TAG ? G::D1 : 1];
+    __shared__ uint32_t sp1[TAG ? 1 : G::SQ];
+    __shared__ uint32_t q2v[G::D2];
+    __shared__ uint16_t q2t[(HAS_E && TAG) ? G::D2 : 1];
+    __shared__ uint32_t sp2[(HAS_E && !TAG) ? G::SQ : 1];
+    __shared__ uint32_t misc[M_WORDS];
 
     const uint32_t t = threadIdx.x;
     const uint32_t wv = t >> 6;
@@ -270,61 +343,127 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
     const uint32_t modr = a.param[1];
     const bool mod_pow2 = (modm & (modm - 1u)) == 0u;
 
-    if (t == 0) misc[M_NEXT] = atomicAdd(&a.ctl[CTL_CLAIM], 1u);
-    bar();
-    uint32_t g = uni(misc[M_NEXT]);
+    // launches completed so far, as a 24-bit tag in [1, 2^24 - 1] for the look-back words
+    // (the control block only changes after every workgroup of a launch has finished)
+    const uint32_t epoch_tag =
+        uni(__hip_atomic_load(&a.ctl[CTL_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) % 0xFFFFFFu + 1u;
 
-    while (g < a.total_claims) {
-        uint32_t g_next = 0;
-        if (t == 0) g_next = atomicAdd(&a.ctl[CTL_CLAIM], 1u);   // overlaps with this claim
-
-        // stream of this claim: the last with claim_begin <= g
+    // stream of global claim gg: the last with claim_begin <= gg
+    auto stream_of = [&](uint32_t gg) -> uint32_t {
         uint32_t lo = 0, hi = a.n_streams;
         while (hi - lo > 1u) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (a.streams[mid].claim_begin <= g) lo = mid; else hi = mid;
+            if (a.streams[mid].claim_begin <= gg) lo = mid; else hi = mid;
         }
-        const StreamDev &sd = a.streams[lo];
+        return lo;
+    };
+    // this lane's share of the region table of claim gg (loads only; consumed a claim later)
+    auto load_claim = [&](uint32_t gg, ClaimRegs &r) {
+        r.off = r.len = r.ctx = 0;
+        if (gg >= a.total_claims) return;
+        const StreamDev &sd = a.streams[stream_of(gg)];
+        const uint32_t B = sd.parents_per_claim;
+        const uint32_t p0 = (gg - sd.claim_begin) * B;
+        const uint32_t nb = min(B, sd.n_parents - p0);
+        if constexpr (!BYTES) {
+            if (t <= nb) r.off = sd.offsets[p0 + t];
+        } else {
+            if (t < nb) {
+                r.off = sd.offsets[p0 + t];
+                r.len = sd.lengths[p0 + t];
+            }
+        }
+        if constexpr (CTXP) {
+            if (t < nb) r.ctx = sd.pparam[p0 + t];
+        }
+    };
+
+    // claims are taken two ahead: g is worked on, g1 is next (its region table in registers)
+    uint32_t first = 0, second = 0;
+    if (t == 0) {
+        first = atomicAdd(&a.ctl[CTL_CLAIM], 1u);
+        second = atomicAdd(&a.ctl[CTL_CLAIM], 1u);
+        misc[M_NEXT] = first;
+        misc[M_NEXT + 1] = second;
+    }
+    bar();
+    uint32_t g = uni(misc[M_NEXT]);
+    uint32_t g1 = uni(misc[M_NEXT + 1]);
+    ClaimRegs cur;
+    load_claim(g, cur);
+    bar();
+
+    while (g < a.total_claims) {
+        uint32_t g_next = 0;
+        if (t == 0) g_next = atomicAdd(&a.ctl[CTL_CLAIM], 1u);   // the claim after g1
+        ClaimRegs nxt;
+        load_claim(g1, nxt);                                      // consumed at the next claim
+
+        const StreamDev &sd = a.streams[stream_of(g)];
         const uint8_t *elems = (const uint8_t *)sd.elements;
         const uint32_t B = sd.parents_per_claim;
-        const uint32_t p0 = (g - sd.claim_begin) * B;
+        const uint32_t cidx = g - sd.claim_begin;
+        const uint32_t p0 = cidx * B;
         const uint32_t nb = uni(min(B, sd.n_parents - p0));
         const uint32_t nbytes_total = sd.n_elements * EB;
 
         // ---- region table of the claim (enumeration: findCount per parent)
         uint32_t vbeg, vend;
         if constexpr (!BYTES) {
-            for (uint32_t i = t; i <= nb; i += W) V[i] = sd.offsets[p0 + i];
+            if (t <= nb) VT[t] = cur.off;
             if constexpr (CTXP)
-                for (uint32_t i = t; i < nb; i += W) CX[i] = sd.pparam[p0 + i];
+                if (t < nb) CX[t] = cur.ctx;
             bar();
-            vbeg = uni(V[0]);
-            vend = uni(V[nb]);
+            vbeg = uni(VT[0]);
+            vend = uni(VT[nb]);
         } else {
-            uint32_t carry = 0;
-            for (uint32_t i0 = 0; i0 < nb; i0 += W) {
-                const uint32_t i = i0 + t;
-                uint32_t len = 0;
-                if (i < nb) {
-                    SX[i] = sd.offsets[p0 + i];
-                    len = sd.lengths[p0 + i];
-                }
-                uint32_t tot;
-                const uint32_t ex = wg_scan_u32<W>(len, misc, tot);
-                if (i < nb) V[i] = carry + ex;
-                carry += tot;
-                bar();
-            }
-            if (t == 0) V[nb] = carry;
+            if (t < nb) SX[t] = cur.off;
+            uint32_t tot;
+            const uint32_t ex = wg_scan_u32<W>(t < nb ? cur.len : 0u, misc, tot);
+            if (t < nb) VT[t] = ex;
+            if (t == 0) VT[nb] = tot;
             bar();
             vbeg = 0;
-            vend = carry;
+            vend = tot;
         }
-        for (uint32_t i = t; i < nb; i += W) {
-            s_cnt[i] = 0;
-            s_sum[i] = 0ull;
-            s_min[i] = 0xFFFFFFFFu;
-            s_max[i] = 0;
+        if (t < nb) {
+            s_cnt[t] = 0;
+            s_sum[t] = 0ull;
+            s_min[t] = 0xFFFFFFFFu;
+            s_max[t] = 0;
+        }
+
+        // The claim's regions must be ordered and inside the element array before any element
+        // is read; a malformed stream is flagged and its claims are skipped.
+        {
+            bool bad = false;
+            if (t < nb) {
+                if constexpr (!BYTES) {
+                    bad = (VT[t] > VT[t + 1]) || (t + 1u == nb && VT[nb] > sd.n_elements);
+                } else {
+                    const unsigned long long end = (unsigned long long)SX[t] + (VT[t + 1] - VT[t]);
+                    const unsigned long long lim = (t + 1u < nb) ? SX[t + 1] : sd.n_elements;
+                    bad = end > lim;
+                }
+            }
+            if (t == 0) misc[M_BAD] = 0;
+            bar();
+            if (bad) misc[M_BAD] = 1;
+            bar();
+            if (uni(misc[M_BAD])) {
+                if (t == 0) {
+                    atomicOr((unsigned int *)&sd.stats[ST_ERROR], 1u);
+                    if (a.emit_outputs)   // successors of this claim must not wait for it
+                        __hip_atomic_store(&sd.lookback[cidx], ((unsigned long long)epoch_tag << 40) | (2ull << 38),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    misc[M_NEXT] = g_next;
+                }
+                bar();
+                g = g1;
+                g1 = uni(misc[M_NEXT]);
+                cur = nxt;
+                continue;
+            }
         }
 
         // ---- element ring: the claim's byte range, chunked from a 16-byte aligned base
@@ -334,16 +473,16 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
             b1 = vend * 4u;
         } else {
             b0 = nb ? uni(SX[0]) : 0u;
-            b1 = nb ? uni(SX[nb - 1] + (V[nb] - V[nb - 1])) : 0u;
-        }
-        if constexpr (BYTES && TAG) {   // lines are enumerated over the claim's address range
-            vbeg = b0;
-            vend = b1;
+            b1 = nb ? uni(SX[nb - 1] + (VT[nb] - VT[nb - 1])) : 0u;
+            if constexpr (TAG) {   // lines are enumerated over the claim's address range
+                vbeg = b0;
+                vend = b1;
+            }
         }
         const uint32_t A0 = b0 & ~15u;
         const uint32_t nch = (b1 > b0) ? (b1 - A0 + G::CHB - 1u) / G::CHB : 0u;
         uint32_t ld_next = 0, ld_ready = 0;
-        uint32_t partial_mask = 0;   // per lane: chunk-parity bits of a pending partial tail block
+        uint32_t partial_mask = 0;   // per lane: ring slots holding a partial tail block to patch
 
         auto issue = [&]() {
             const uint32_t c = ld_next;
@@ -352,15 +491,13 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
             const uint8_t *src = full ? elems + blk : (const uint8_t *)a.dummy;
             if (!full && blk < nbytes_total) partial_mask |= 1u << (c % G::NS);
             __builtin_amdgcn_global_load_lds((glb_void_t *)src,
-                                             (lds_void_t *)(ring + (c % G::NS) * G::CHB + wv * 1024u),
-                                             16, 0, 0);
+                                             (lds_void_t *)(ring + (c % G::NS) * G::CHB + wv * 1024u), 16, 0, 0);
             ld_next = c + 1u;
         };
         // make chunks [0, k] readable
         auto ready_upto = [&](uint32_t k) {
             while (ld_ready <= k) {
-                const uint32_t after = ld_next - 1u - ld_ready;
-                wait_vm_n(after);
+                wait_vm_n(ld_next - 1u - ld_ready);
                 if (partial_mask & (1u << (ld_ready % G::NS))) {
                     partial_mask &= ~(1u << (ld_ready % G::NS));
                     const uint32_t blk = A0 + ld_ready * G::CHB + t * 16u;
@@ -374,20 +511,189 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         // issue every chunk whose ring slot is free: chunk ld_next reuses the slot of
         // chunk ld_next - NS, which must end at or before need_from
         auto refill = [&](uint32_t need_from) {
-            while (ld_next < nch &&
-                   (ld_next < G::NS || A0 + (ld_next - G::NS + 1u) * G::CHB <= need_from))
-                issue();
+            while (ld_next < nch && (ld_next < G::NS || A0 + (ld_next - G::NS + 1u) * G::CHB <= need_from)) issue();
         };
         auto ring_off = [&](uint32_t addr) -> uint32_t { return ring_base + ((addr - A0) & (G::RING - 1u)); };
+        auto ring_drain = [&]() {
+            if (ld_ready < ld_next) {   // chunks issued beyond what was read (look-ahead margin)
+                wait_vm<0>();
+                bar();
+            }
+            ld_next = 0;
+            ld_ready = 0;
+            partial_mask = 0;
+        };
+        // Make the bytes of the enumerating node's next ensemble (fpos, e items) readable:
+        // one byte before it (word starts look back) and, for the text kind, a look-ahead
+        // margin for the word-length node.  False only on an internal logic error.
+        auto f_stage = [&](uint32_t fpos_, uint32_t fj_, uint32_t e) -> bool {
+            if (!e) return true;
+            uint32_t need_lo, need_hi;
+            if constexpr (!BYTES) {
+                need_lo = fpos_ * 4u;
+                need_hi = (fpos_ + e) * 4u;
+            } else {
+                const uint32_t adr0 = TAG ? fpos_ : uni(SX[fj_]) + (fpos_ - uni(VT[fj_]));
+                need_lo = adr0 > A0 ? adr0 - 1u : A0;
+                need_hi = adr0 + e + 64u;
+                if (need_hi > b1) need_hi = b1;
+            }
+            refill(need_lo);
+            const uint32_t last_chunk = (need_hi - 1u - A0) / G::CHB;
+            // one ensemble spans far less than NS-1 chunks, so refill has issued it
+            if (ld_next <= last_chunk) return false;
+            ready_upto(last_chunk);
+            return true;
+        };
+        // Region of enumeration position v (tag strategy): the largest j whose start is <= v,
+        // by element index (CSR) or by byte address (lines), searching from jlo_.
+        auto f_region = [&](uint32_t v, uint32_t jlo_) -> uint32_t {
+            const uint32_t *key = BYTES ? SX : VT;
+            uint32_t l2 = jlo_, h2s = nb;
+            while (h2s - l2 > 1u) {
+                const uint32_t m = (l2 + h2s) >> 1;
+                if (key[m] <= v) l2 = m; else h2s = m;
+            }
+            return l2;
+        };
+        // The enumerating node for one firing: items fpos + k*W + lane, k < V, of which the
+        // first e are real.  Fetches each element under its parent's context and applies the
+        // first stage.  keep[k], item[k], aux[k], reg[k] describe item k of this lane.
+        auto f_fire = [&](uint32_t fpos_, uint32_t fj_, uint32_t jlo_, uint32_t e, uint32_t (&keep)[V],
+                          uint32_t (&item)[V], uint32_t (&aux)[V], uint32_t (&reg)[V]) {
+            uint32_t jr = jlo_;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                keep[k] = 0;
+                aux[k] = 0;
+                const uint32_t i = (uint32_t)k * W + t;
+                const uint32_t v = fpos_ + (i < e ? i : 0u);
+                if constexpr (TAG) {
+                    jr = (i < e) ? f_region(v, jr) : jr;
+                    reg[k] = jr;
+                } else {
+                    reg[k] = fj_;
+                }
+            }
+            if constexpr (!BYTES) {
+                uint32_t addr[V], x[V];
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const uint32_t i = (uint32_t)k * W + t;
+                    addr[k] = ring_off((fpos_ + (i < e ? i : 0u)) * 4u);
+                }
+                ring_read<V>(addr, x);
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const bool act = (uint32_t)k * W + t < e;
+                    item[k] = x[k];
+                    if constexpr (KIND == RS_MODFILTER) {
+                        keep[k] = act && (mod_pow2 ? ((x[k] & (modm - 1u)) == modr) : (x[k] % modm == modr));
+                    } else if constexpr (KIND == RS_HASH_EXPAND) {
+                        const uint32_t h = fmix32(x[k] ^ salt_key(0));
+                        keep[k] = act && (h & 1u);
+                        aux[k] = (h >> 1) & 3u;
+                    } else {
+                        keep[k] = act && x[k] < CX[reg[k]];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const uint32_t i = (uint32_t)k * W + t;
+                    const uint32_t v = fpos_ + i;
+                    const uint32_t j = reg[k];
+                    // signal: v is VT[j] plus the line-relative position; tag: v is the address
+                    const uint32_t ls = SX[j];
+                    const uint32_t adr = TAG ? v : ls + (v - VT[j]);
+                    item[k] = adr;
+                    const bool in_line = i < e && (!TAG || adr < ls + (VT[j + 1] - VT[j]));
+                    if (in_line) {
+                        const uint32_t b = ring_u8(ring_off(adr));
+                        const uint32_t prev = (adr == ls) ? 32u : ring_u8(ring_off(adr - 1u));
+                        keep[k] = (b != 32u) && (prev == 32u);
+                    }
+                }
+            }
+        };
+
+        bool failed = false;
+        // ---- ordered output stream: count this claim's outputs, then learn its base from the
+        // claims before it (decoupled look-back over the stream's claims) before producing.
+        uint32_t out_base_lo = 0, out_base_hi = 0;
+        if (a.emit_outputs) {
+            refill(A0);
+            uint32_t fpos = vbeg, fj = 0, jlo = 0;
+            bool fdone = TAG ? (vbeg >= vend) : (nb == 0);
+            unsigned long long n_out = 0;
+            while (!fdone) {
+                const uint32_t e = TAG ? min(EW, vend - fpos) : min(EW, uni(VT[fj + 1]) - fpos);
+                if (!f_stage(fpos, fj, e)) {
+                    failed = true;
+                    break;
+                }
+                uint32_t keep[V], item[V], aux[V], reg[V], nout[V], off[V], tot;
+                f_fire(fpos, fj, jlo, e, keep, item, aux, reg);
+#pragma unroll
+                for (int k = 0; k < V; ++k) nout[k] = keep[k] ? (KIND == RS_HASH_EXPAND ? aux[k] : 1u) : 0u;
+                ens_scan<W, V, true>(nout, off, tot, misc);
+                n_out += tot;
+                if constexpr (TAG) {
+#pragma unroll
+                    for (int k = 0; k < V; ++k)
+                        if ((uint32_t)k * W + t == e - 1u) misc[M_JLAST] = reg[k];
+                }
+                fpos += e;
+                bar();
+                if constexpr (TAG) {
+                    jlo = uni(misc[M_JLAST]);
+                    fdone = (fpos == vend);
+                } else {
+                    if (fpos == uni(VT[fj + 1])) {
+                        ++fj;
+                        fdone = (fj == nb);
+                    }
+                }
+            }
+            ring_drain();
+            // look-back: words are (epoch tag << 40) | (flag << 38) | value, flag 1 = this claim's
+            // own count, flag 2 = inclusive prefix through this claim
+            if (t == 0) {
+                unsigned long long *lb = sd.lookback;
+                const unsigned long long tagw = (unsigned long long)epoch_tag << 40;
+                const unsigned long long mask38 = (1ull << 38) - 1ull;
+                __hip_atomic_store(&lb[cidx], tagw | (1ull << 38) | (n_out & mask38), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                unsigned long long prefix = 0;
+                for (uint32_t i = cidx; i-- > 0;) {
+                    unsigned long long w;
+                    for (;;) {
+                        w = __hip_atomic_load(&lb[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((w >> 40) == (unsigned long long)epoch_tag && ((w >> 38) & 3ull)) break;
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    prefix += w & mask38;
+                    if (((w >> 38) & 3ull) == 2ull) break;
+                }
+                __hip_atomic_store(&lb[cidx], tagw | (2ull << 38) | ((prefix + n_out) & mask38), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                misc[M_BASE_LO] = (uint32_t)prefix;
+                misc[M_BASE_HI] = (uint32_t)(prefix >> 32);
+            }
+            bar();
+            out_base_lo = uni(misc[M_BASE_LO]);
+            out_base_hi = uni(misc[M_BASE_HI]);
+        }
+        uint32_t *const out_items = sd.out_items;
+        unsigned long long out_rank = ((unsigned long long)out_base_hi << 32) | out_base_lo;
 
         refill(A0);
-        bar();   // slots initialised, region table visible
 
         // ---- node state (all uniform)
         uint32_t h1 = 0, t1 = 0, sh1 = 0, st1 = 0;
         uint32_t h2 = 0, t2 = 0, sh2 = 0, st2 = 0;
-        // enumerating node: signal strategy walks region j at position fpos;
-        // tag strategy walks ensembles of W consecutive elements from fpos.
+        // enumerating node: signal strategy walks region fj at position fpos;
+        // tag strategy walks ensembles of EW consecutive positions from fpos.
         uint32_t fj = 0, fpos = vbeg, jlo = 0, ej = 0;
         bool fdone = TAG ? (vbeg >= vend) : (nb == 0);
         uint32_t a_items = 0;                 // items aggregated since the last signal (signal strategy)
@@ -399,7 +705,6 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         // element and per region, so this bound only trips on a scheduling error
         const unsigned long long iter_cap = 8ull * ((unsigned long long)(vend - vbeg) + nb) + 64ull;
         unsigned long long iters = 0;
-        bool failed = false;
 
         auto flush_tag = [&]() {
             if (acc.cnt) {
@@ -412,53 +717,69 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         };
 
         for (;;) {
-            if (++iters > iter_cap) { failed = true; break; }
+            if (++iters > iter_cap) {
+                failed = true;
+                break;
+            }
             // ---------------- A: the aggregating node (drains first)
             {
                 uint32_t &h = HAS_E ? h2 : h1;
-                uint32_t &tq = HAS_E ? t2 : t1;
                 uint32_t &sh = HAS_E ? sh2 : sh1;
-                const uint32_t &stq = HAS_E ? st2 : st1;
+                const uint32_t tq = HAS_E ? t2 : t1;
+                const uint32_t stq = HAS_E ? st2 : st1;
                 const uint32_t *qv = HAS_E ? q2v : q1v;
-                const uint32_t *qt = HAS_E ? q2t : q1t;
+                const uint16_t *qt = HAS_E ? q2t : q1t;
                 const uint32_t *sp = HAS_E ? sp2 : sp1;
                 constexpr uint32_t D = HAS_E ? G::D2 : G::D1;
                 const bool up_done = HAS_E ? (fdone && h1 == t1) : fdone;
                 uint32_t e = 0;
-                bool fire = false, sig_next = false;
+                bool fire = false;
                 if (!TAG && sh < stq) {
-                    const uint32_t credit = uni(sp[sh & (D - 1u)]) - h;
-                    e = credit < (uint32_t)W ? credit : (uint32_t)W;
+                    const uint32_t credit = uni(sp[sh & (G::SQ - 1u)]) - h;
+                    e = credit < EW ? credit : EW;
                     fire = true;
-                    sig_next = true;
                 } else {
                     const uint32_t n = tq - h;
-                    if (n >= (uint32_t)W) { e = W; fire = true; }
-                    else if (up_done && n > 0) { e = n; fire = true; }
+                    if (n >= EW) {
+                        e = EW;
+                        fire = true;
+                    } else if (up_done && n > 0) {
+                        e = n;
+                        fire = true;
+                    }
                 }
                 if (fire) {
                     if (e) {
-                        if (t < e) {
-                            const uint32_t pos = (h + t) & (D - 1u);
-                            const uint32_t y = qv[pos];
-                            if constexpr (TAG) {
-                                const uint32_t tg = qt[pos];
-                                if (tg != acc_tag) {
-                                    flush_tag();
-                                    acc_tag = tg;
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            const uint32_t i = (uint32_t)k * W + t;
+                            if (i < e) {
+                                const uint32_t pos = (h + i) & (D - 1u);
+                                uint32_t y = qv[pos];
+                                // the expansion's children arrive as pre-images x ^ K(j+1);
+                                // finishing the hash here completes H(x, j+1)
+                                if constexpr (KIND == RS_HASH_EXPAND) y = fmix32(y);
+                                if (out_items) out_items[out_rank + i] = y;   // serial order
+                                if constexpr (TAG) {
+                                    const uint32_t tg = qt[pos];
+                                    if (tg != acc_tag) {
+                                        flush_tag();
+                                        acc_tag = tg;
+                                    }
                                 }
+                                acc_add(acc, y);
                             }
-                            acc_add(acc, y);
                         }
                         h += e;
                         a_items += e;
+                        out_rank += e;
                         st_fire[2] += 1;
                         st_items[2] += e;
-                        st_full[2] += (e == (uint32_t)W);
+                        st_full[2] += (e == EW);
                     }
                     if constexpr (!TAG) {
                         // signal phase: consume every slot that no item precedes
-                        while (sh < stq && uni(sp[sh & (D - 1u)]) == h) {
+                        while (sh < stq && uni(sp[sh & (G::SQ - 1u)]) == h) {
                             const uint32_t j = uni(qv[h & (D - 1u)]);
                             if (a_items) {
                                 const Acc r = wg_reduce<W>(acc, misc);
@@ -476,7 +797,6 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                             st_sig[2] += 1;
                         }
                     }
-                    (void)sig_next;
                     bar();
                     continue;
                 }
@@ -488,63 +808,83 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                 const uint32_t space = G::D2 - (t2 - h2) - (TAG ? 0u : 1u);
                 const uint32_t cap = space / KE;
                 if (!TAG && sh1 < st1) {
-                    const uint32_t credit = uni(sp1[sh1 & (G::D1 - 1u)]) - h1;
-                    e = min(min(credit, (uint32_t)W), cap);
-                    fire = (credit == 0) ? (space >= 1u) : (e > 0);
+                    const uint32_t credit = uni(sp1[sh1 & (G::SQ - 1u)]) - h1;
+                    e = min(min(credit, EW), cap);
+                    fire = (credit == 0) ? (space >= 1u && st2 - sh2 < G::SQ) : (e > 0);
                 } else {
                     const uint32_t n = t1 - h1;
-                    if (n >= (uint32_t)W || (fdone && n > 0)) {
-                        e = min(min(n, (uint32_t)W), cap);
+                    if (n >= EW || (fdone && n > 0)) {
+                        e = min(min(n, EW), cap);
                         fire = e > 0;
                     }
                 }
                 if (fire) {
                     if (e) {
-                        uint32_t nout = 0, y0 = 0, y1 = 0, y2 = 0, tg = 0;
-                        if (t < e) {
-                            const uint32_t pos = (h1 + t) & (G::D1 - 1u);
-                            const uint32_t x = q1v[pos];
-                            if constexpr (TAG) tg = q1t[pos];
-                            if constexpr (KIND == RS_HASH_EXPAND) {
-                                nout = q1a[pos];
-                                y0 = fmix32(x ^ salt_key(1));
-                                y1 = fmix32(x ^ salt_key(2));
-                                y2 = fmix32(x ^ salt_key(3));
-                            } else {   // word length: run of non-space bytes from the start, within the line
-                                const uint32_t j = TAG ? tg : ej;
-                                const uint32_t le = SX[j] + (V[j + 1] - V[j]);
-                                const uint32_t wlo = A0 + (ld_next > G::NS ? ld_next - G::NS : 0u) * G::CHB;
-                                const uint32_t whi = A0 + ld_ready * G::CHB;
-                                uint32_t p = x;
-                                while (p < le) {
-                                    const uint32_t b = (p >= wlo && p < whi) ? ring_u8(ring_off(p)) : (uint32_t)elems[p];
-                                    if (b == 32u) break;
-                                    ++p;
+                        uint32_t nout[V], x[V], tg[V], off[V], tot;
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            const uint32_t i = (uint32_t)k * W + t;
+                            nout[k] = 0;
+                            x[k] = 0;
+                            tg[k] = 0;
+                            if (i < e) {
+                                const uint32_t pos = (h1 + i) & (G::D1 - 1u);
+                                x[k] = q1v[pos];
+                                if constexpr (TAG) tg[k] = q1t[pos];
+                                if constexpr (KIND == RS_HASH_EXPAND) {
+                                    nout[k] = q1a[pos];
+                                } else {
+                                    // word length: run of non-space bytes from the start, within the line
+                                    const uint32_t j = TAG ? tg[k] : ej;
+                                    const uint32_t le = SX[j] + (VT[j + 1] - VT[j]);
+                                    const uint32_t wlo = A0 + (ld_next > G::NS ? ld_next - G::NS : 0u) * G::CHB;
+                                    const uint32_t whi = A0 + ld_ready * G::CHB;
+                                    uint32_t p = x[k];
+                                    while (p < le) {
+                                        const uint32_t b =
+                                            (p >= wlo && p < whi) ? ring_u8(ring_off(p)) : (uint32_t)elems[p];
+                                        if (b == 32u) break;
+                                        ++p;
+                                    }
+                                    x[k] = p - x[k];
+                                    nout[k] = 1;
                                 }
-                                y0 = p - x;
-                                nout = 1;
                             }
                         }
-                        uint32_t tot;
-                        const uint32_t off = wg_scan3<W>(nout, misc, tot);
-                        if (t < e) {
-                            const uint32_t base = t2 + off;
-                            if (nout > 0) { q2v[base & (G::D2 - 1u)] = y0; if constexpr (TAG) q2t[base & (G::D2 - 1u)] = tg; }
-                            if (nout > 1) { q2v[(base + 1u) & (G::D2 - 1u)] = y1; if constexpr (TAG) q2t[(base + 1u) & (G::D2 - 1u)] = tg; }
-                            if (nout > 2) { q2v[(base + 2u) & (G::D2 - 1u)] = y2; if constexpr (TAG) q2t[(base + 2u) & (G::D2 - 1u)] = tg; }
+                        ens_scan<W, V, KE == 3>(nout, off, tot, misc);
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            const uint32_t base = t2 + off[k];
+                            if constexpr (KIND == RS_HASH_EXPAND) {
+                                // child j of x leaves as its pre-image x ^ K(j+1)
+                                if (nout[k] > 0) q2v[base & (G::D2 - 1u)] = x[k] ^ salt_key(1);
+                                if (nout[k] > 1) q2v[(base + 1u) & (G::D2 - 1u)] = x[k] ^ salt_key(2);
+                                if (nout[k] > 2) q2v[(base + 2u) & (G::D2 - 1u)] = x[k] ^ salt_key(3);
+                                if constexpr (TAG) {
+                                    if (nout[k] > 0) q2t[base & (G::D2 - 1u)] = (uint16_t)tg[k];
+                                    if (nout[k] > 1) q2t[(base + 1u) & (G::D2 - 1u)] = (uint16_t)tg[k];
+                                    if (nout[k] > 2) q2t[(base + 2u) & (G::D2 - 1u)] = (uint16_t)tg[k];
+                                }
+                            } else {
+                                if (nout[k]) {
+                                    q2v[base & (G::D2 - 1u)] = x[k];
+                                    if constexpr (TAG) q2t[base & (G::D2 - 1u)] = (uint16_t)tg[k];
+                                }
+                            }
                         }
                         h1 += e;
                         t2 += tot;
                         st_fire[1] += 1;
                         st_items[1] += e;
-                        st_full[1] += (e == (uint32_t)W);
+                        st_full[1] += (e == EW);
                     }
                     if constexpr (!TAG) {
-                        while (sh1 < st1 && uni(sp1[sh1 & (G::D1 - 1u)]) == h1 && G::D2 - (t2 - h2) >= 1u) {
+                        while (sh1 < st1 && uni(sp1[sh1 & (G::SQ - 1u)]) == h1 && G::D2 - (t2 - h2) >= 1u &&
+                               st2 - sh2 < G::SQ) {
                             const uint32_t j = uni(q1v[h1 & (G::D1 - 1u)]);
                             if (t == 0) {
                                 q2v[t2 & (G::D2 - 1u)] = j;
-                                sp2[st2 & (G::D2 - 1u)] = t2;
+                                sp2[st2 & (G::SQ - 1u)] = t2;
                             }
                             ++t2;
                             ++st2;
@@ -563,102 +903,47 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                 uint32_t e, j_sig = 0;
                 bool ends_region = false;
                 if constexpr (TAG) {
-                    e = min((uint32_t)W, vend - fpos);
+                    e = min(EW, vend - fpos);
                 } else {
-                    const uint32_t rend = uni(V[fj + 1]);
-                    e = min((uint32_t)W, rend - fpos);
+                    const uint32_t rend = uni(VT[fj + 1]);
+                    e = min(EW, rend - fpos);
                     ends_region = (fpos + e == rend);
                     j_sig = fj;
                 }
                 const uint32_t space1 = G::D1 - (t1 - h1);
-                if (space1 >= e + (ends_region ? 1u : 0u)) {
-                    // bytes this ensemble reads (plus one byte before it and a look-ahead
-                    // margin for the word-length node under the text kind)
-                    uint32_t need_lo, need_hi;
-                    if constexpr (!BYTES) {
-                        need_lo = fpos * 4u;
-                        need_hi = (fpos + e) * 4u;
-                    } else {
-                        const uint32_t adr0 = TAG ? fpos : uni(SX[fj]) + (fpos - uni(V[fj]));
-                        need_lo = adr0 > A0 ? adr0 - 1u : A0;
-                        need_hi = adr0 + e + 64u;
-                        if (need_hi > b1) need_hi = b1;
+                const bool sig_ok = TAG || !ends_region || (st1 - sh1 < G::SQ);
+                if (space1 >= e + (ends_region ? 1u : 0u) && sig_ok) {
+                    if (!f_stage(fpos, fj, e)) {
+                        failed = true;
+                        break;
                     }
-                    if (e) {
-                        refill(need_lo);
-                        const uint32_t last_chunk = (need_hi - 1u - A0) / G::CHB;
-                        // the span of one ensemble is far below (NS-1) chunks, so refill has
-                        // always issued it; anything else is a logic error
-                        if (ld_next <= last_chunk) { failed = true; break; }
-                        ready_upto(last_chunk);
-                    }
-                    uint32_t keep = 0, item = 0, aux = 0, tg = 0;
-                    if (t < e) {
-                        const uint32_t v = fpos + t;
-                        uint32_t j;
+                    uint32_t keep[V], item[V], aux[V], reg[V], off[V], tot;
+                    f_fire(fpos, fj, jlo, e, keep, item, aux, reg);
+                    ens_scan<W, V, false>(keep, off, tot, misc);
+#pragma unroll
+                    for (int k = 0; k < V; ++k) {
+                        if (keep[k]) {
+                            const uint32_t pos = (t1 + off[k]) & (G::D1 - 1u);
+                            q1v[pos] = item[k];
+                            if constexpr (KIND == RS_HASH_EXPAND) q1a[pos] = (uint8_t)aux[k];
+                            if constexpr (TAG) q1t[pos] = (uint16_t)reg[k];
+                        }
                         if constexpr (TAG) {
-                            // largest j with start(j) <= v: element index (CSR) or byte address (lines)
-                            const uint32_t *key = BYTES ? SX : V;
-                            uint32_t l2 = jlo, h2s = nb;
-                            while (h2s - l2 > 1u) {
-                                const uint32_t m = (l2 + h2s) >> 1;
-                                if (key[m] <= v) l2 = m; else h2s = m;
-                            }
-                            j = l2;
-                            tg = j;
-                        } else {
-                            j = fj;
+                            if ((uint32_t)k * W + t == e - 1u) misc[M_JLAST] = reg[k];
                         }
-                        if constexpr (KIND == RS_MODFILTER) {
-                            const uint32_t x = ring_u32(ring_off(v * 4u));
-                            keep = mod_pow2 ? ((x & (modm - 1u)) == modr) : (x % modm == modr);
-                            item = x;
-                        } else if constexpr (KIND == RS_HASH_EXPAND) {
-                            const uint32_t x = ring_u32(ring_off(v * 4u));
-                            const uint32_t h = fmix32(x ^ salt_key(0));
-                            keep = h & 1u;
-                            item = x;
-                            aux = (h >> 1) & 3u;
-                        } else if constexpr (KIND == RS_GRAPH_THRESH) {
-                            const uint32_t x = ring_u32(ring_off(v * 4u));
-                            keep = x < CX[j];
-                            item = x;
-                        } else {
-                            // signal: v is the line-relative position plus V[j]; tag: v is the address
-                            const uint32_t ls = SX[j];
-                            const uint32_t adr = TAG ? v : ls + (v - V[j]);
-                            const bool in_line = !TAG || adr < ls + (V[j + 1] - V[j]);
-                            if (in_line) {
-                                const uint32_t b = ring_u8(ring_off(adr));
-                                const uint32_t prev = (adr == ls) ? 32u : ring_u8(ring_off(adr - 1u));
-                                keep = (b != 32u) && (prev == 32u);
-                            }
-                            item = adr;
-                        }
-                    }
-                    uint32_t tot;
-                    const uint32_t off = wg_scan3<W>(keep, misc, tot);
-                    if (keep) {
-                        const uint32_t pos = (t1 + off) & (G::D1 - 1u);
-                        q1v[pos] = item;
-                        if constexpr (KIND == RS_HASH_EXPAND) q1a[pos] = aux;
-                        if constexpr (TAG) q1t[pos] = tg;
-                    }
-                    if constexpr (TAG) {
-                        if (t == e - 1u) misc[M_JLAST] = tg;
                     }
                     t1 += tot;
                     fpos += e;
                     if (e) {
                         st_fire[0] += 1;
                         st_items[0] += e;
-                        st_full[0] += (e == (uint32_t)W);
+                        st_full[0] += (e == EW);
                     }
                     if constexpr (!TAG) {
                         if (ends_region) {
                             if (t == 0) {
                                 q1v[t1 & (G::D1 - 1u)] = j_sig;
-                                sp1[st1 & (G::D1 - 1u)] = t1;
+                                sp1[st1 & (G::SQ - 1u)] = t1;
                             }
                             ++t1;
                             ++st1;
@@ -685,21 +970,18 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
             flush_tag();
             bar();
         }
-        if (ld_ready < ld_next) {   // chunks issued beyond what was read (look-ahead margin)
-            wait_vm<0>();
-            bar();
-        }
+        ring_drain();
         if (failed && t == 0) atomicOr(&a.ctl[CTL_ERROR], 1u);
 
         // ---- end(): one record per parent, written once
-        for (uint32_t i = t; i < nb; i += W) {
-            const uint32_t p = p0 + i;
-            if (a.agg_fields & RS_COUNT) sd.agg_count[p] = s_cnt[i];
-            if (a.agg_fields & RS_SUM) sd.agg_sum[p] = s_sum[i];
-            if (a.agg_fields & RS_MIN) sd.agg_min[p] = s_min[i];
-            if (a.agg_fields & RS_MAX) sd.agg_max[p] = s_max[i];
+        if (t < nb) {
+            const uint32_t p = p0 + t;
+            if (a.agg_fields & RS_COUNT) sd.agg_count[p] = s_cnt[t];
+            if (a.agg_fields & RS_SUM) sd.agg_sum[p] = s_sum[t];
+            if (a.agg_fields & RS_MIN) sd.agg_min[p] = s_min[t];
+            if (a.agg_fields & RS_MAX) sd.agg_max[p] = s_max[t];
         }
-        if (a.collect_stats && t == 0 && sd.stats) {
+        if (a.collect_stats && t == 0) {
             for (int k = 0; k < 3; ++k) {
                 atomicAdd(&sd.stats[ST_FIRINGS + k], (unsigned long long)st_fire[k]);
                 atomicAdd(&sd.stats[ST_ITEMS + k], (unsigned long long)st_items[k]);
@@ -709,7 +991,9 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         }
         if (t == 0) misc[M_NEXT] = g_next;
         bar();
-        g = uni(misc[M_NEXT]);
+        g = g1;
+        g1 = uni(misc[M_NEXT]);
+        cur = nxt;
     }
 
     // last workgroup out returns the control block to zero for the next launch
@@ -724,21 +1008,19 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
     }
 }
 
-}  // namespace rs
-
 // ---------------------------------------------------------------- launch table
-
-namespace rs {
 
 using KernelFn = void (*)(LaunchArgs);
 
+// Ensemble width w = W * V: W lanes per workgroup, V items per lane per firing.
 template <int KIND, int STRAT>
 static KernelFn pick_width(uint32_t w) {
     switch (w) {
-        case 64: return rs_pipeline<KIND, STRAT, 64>;
-        case 128: return rs_pipeline<KIND, STRAT, 128>;
-        case 256: return rs_pipeline<KIND, STRAT, 256>;
-        case 512: return rs_pipeline<KIND, STRAT, 512>;
+        case 64: return rs_pipeline<KIND, STRAT, 64, 1>;
+        case 128: return rs_pipeline<KIND, STRAT, 128, 1>;
+        case 256: return rs_pipeline<KIND, STRAT, 256, 1>;
+        case 512: return rs_pipeline<KIND, STRAT, 256, 2>;
+        case 1024: return rs_pipeline<KIND, STRAT, 256, 4>;
         default: return nullptr;
     }
 }
@@ -758,15 +1040,34 @@ static KernelFn pick(uint32_t kind, uint32_t s, uint32_t w) {
     }
 }
 
+uint32_t lanes_of(uint32_t ensemble_width) { return ensemble_width > 256 ? 256u : ensemble_width; }
+
+// ---------------------------------------------------------------- HBM probe
+
+// Plain copy, 16 bytes per lane per step, grid-stride: the achievable-bandwidth reference
+// for the pipeline kernels and the known-size copy that calibrates traffic counters.
+__global__ void __launch_bounds__(256) probe_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                  unsigned long long n16) {
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+int launch_probe_copy(const void *src, void *dst, unsigned long long bytes, uint32_t n_cu, void *stream) {
+    hipLaunchKernelGGL(probe_copy, dim3(n_cu * 4), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src,
+                       (uint4 *)dst, bytes / 16);
+    return (int)hipGetLastError();
+}
+
 bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width) {
     return pick(kind, strategy, width) != nullptr;
 }
 
-int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a,
-                    uint32_t grid, void *stream) {
+int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a, uint32_t grid,
+                    void *stream) {
     KernelFn k = pick(kind, strategy, width);
     if (!k) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(width), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
@@ -774,49 +1075,8 @@ int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width) {
     KernelFn k = pick(kind, strategy, width);
     if (!k) return 0;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)width, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)lanes_of(width), 0) != hipSuccess) return 0;
     return n;
-}
-
-}  // namespace rs
-
-// ---------------------------------------------------------------- region validation
-
-namespace rs {
-
-// Checks borrowed device regions before any pipeline kernel reads through them:
-// CSR offsets non-decreasing and within the element array, or start+length regions
-// in order, disjoint and within the array.  Records the first bad parent.
-__global__ void validate_regions(const uint32_t *offs, const uint32_t *lens, uint32_t P, uint32_t n,
-                                 uint32_t *bad) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    bool ok;
-    if (!lens) {
-        ok = offs[i] <= offs[i + 1] && offs[i + 1] <= n;
-    } else {
-        const unsigned long long end = (unsigned long long)offs[i] + lens[i];
-        ok = end <= n && (i + 1 == P || end <= offs[i + 1]);
-    }
-    if (!ok) atomicMin(bad, i);
-}
-
-int validate_device_regions(const uint32_t *offs, const uint32_t *lens, uint32_t P, uint32_t n, void *stream) {
-    uint32_t *bad = nullptr;
-    hipError_t e = hipMalloc(&bad, 4);
-    if (e != hipSuccess) return -(int)e;
-    uint32_t h = 0xFFFFFFFFu;
-    e = hipMemcpyAsync(bad, &h, 4, hipMemcpyHostToDevice, (hipStream_t)stream);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(validate_regions, dim3((P + 255) / 256), dim3(256), 0, (hipStream_t)stream, offs, lens, P,
-                           n, bad);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
-    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
-    (void)hipFree(bad);
-    if (e != hipSuccess) return -(int)e;
-    return h == 0xFFFFFFFFu ? 0 : (int)(h + 1u);
 }
 
 }  // namespace rs

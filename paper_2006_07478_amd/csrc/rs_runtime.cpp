@@ -1,17 +1,28 @@
 // Host runtime behind the C ABI (include/regionstream.h).
 //
-// A pipeline owns a HIP stream, a small device control block that the persistent
-// kernel returns to zero on exit, and the device state of its streams.  run()
-// gathers every pushed stream that fits the HBM budget into one work table and
-// launches the persistent kernel once for all of them (§2.2: processors compete
-// for a common input through atomics and the kernel returns only when the input
-// is consumed).
+// A pipeline owns two HIP streams of default priority (or borrows the caller's), and
+// the device state of its streams.  run() gathers every pushed stream that fits the
+// HBM budget into one batch: a device work table plus its own control block, and one
+// launch of the persistent kernel in which workgroups compete for parent batches
+// through a device atomic and return only when every claim is done (§2.2).  Batches
+// launched back to back alternate between the two HIP streams, so a new batch starts
+// on compute units that the previous one's last claims no longer use.
+//
+// When the description leaves the strategy or the ensemble width open, the first
+// run() times every candidate on the first stream of the batch and keeps the fastest
+// (§5: the right mechanism depends on elements per region against the SIMD width;
+// §6 asks for that choice to be made from measurement).  Choices are cached on disk
+// per kind and mean-region-length bucket.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <deque>
+#include <thread>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -46,47 +57,70 @@ int fail(int code, const char *fmt, ...) {
 uint32_t k_max_of(uint32_t kind) { return kind == RS_HASH_EXPAND ? 3u : 1u; }
 uint32_t elem_bytes_of(uint32_t kind) { return kind == RS_TEXT_WORDS ? 1u : 4u; }
 
+const uint32_t kWidths[] = {64, 128, 256, 512, 1024};
+
+// Look-back words carry the batch's launch count modulo 2^24 - 1 as a tag.
+constexpr uint64_t kEpochCycle = 0xFFFFFFull;
+
 enum StreamState { S_PUSHED = 0, S_LAUNCHED = 1, S_DONE = 2 };
 
 struct DevBuf {
     void *p = nullptr;
-    ~DevBuf() {
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    void reset() {
         if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
     }
-    int alloc(size_t bytes) {
-        if (bytes == 0) bytes = 16;
-        hipError_t e = hipMalloc(&p, bytes);
+    int alloc(size_t n) {
+        reset();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
         if (e != hipSuccess) {
             p = nullptr;
-            return fail(RS_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+            return fail(RS_ENOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
         }
+        bytes = n;
         return RS_OK;
     }
 };
+
+struct Batch;
 
 struct Stream {
     uint64_t id = 0;
     StreamState state = S_PUSHED;
     uint32_t n_parents = 0, n_elements = 0;
+    double mean_len = 0;
     const void *elements = nullptr;
     const uint32_t *offsets = nullptr, *lengths = nullptr, *pparam = nullptr;
     DevBuf own_elements, own_offsets, own_lengths, own_pparam;
     DevBuf count, sum, min, max, stats;
-    uint32_t B = 1, n_claims = 0;
+    DevBuf out, lookback;          // ordered output stream and its per-claim look-back words
+    uint64_t out_cap = 0;
+    uint32_t B = 1, n_claims = 0;  // parents per claim and claims, planned at launch
     uint64_t footprint = 0;
-    uint64_t batch = 0;            // launch batch this stream ran in
-    std::shared_ptr<hipEvent_t> done;
+    uint64_t batch = 0;            // batch this stream runs in
 };
 
 struct Batch {
     std::vector<uint64_t> ids;
-    DevBuf table;
+    DevBuf table, ctl;
     uint32_t total_claims = 0;
     uint32_t grid = 0;
+    uint32_t strategy = 0, width = 0;
     rs::LaunchArgs args{};
+    hipStream_t lane = nullptr;
+    uint64_t launches = 0;         // launches of this batch (its control block counts them too)
     hipGraphExec_t graph = nullptr;
+    hipEvent_t done = nullptr;
     ~Batch() {
         if (graph) (void)hipGraphExecDestroy(graph);
+        if (done) (void)hipEventDestroy(done);
     }
 };
 
@@ -96,10 +130,12 @@ struct rs_pipeline {
     rs_pipeline_desc d{};
     int device = 0;
     int n_cu = 0;
-    hipStream_t own_stream = nullptr;
-    hipStream_t stream = nullptr;
-    DevBuf ctl, dummy;
+    hipStream_t own[2] = {nullptr, nullptr};
+    hipStream_t user_stream = nullptr;
+    bool one_lane = false;         // every batch on the first lane (the per-stream baseline)
+    DevBuf dummy;
     uint32_t width = 0, strategy = 0;
+    bool configured = false;
     uint64_t next_id = 1, next_batch = 1;
     uint64_t admitted_bytes = 0;
     std::map<uint64_t, std::unique_ptr<Stream>> streams;
@@ -109,15 +145,43 @@ struct rs_pipeline {
 
 namespace {
 
-// Pick ensemble width and strategy for a pipeline whose description left them open,
-// from the mean region length of the first stream (the paper's §5 observation: the
-// right mechanism depends on elements per region relative to the SIMD width).
-void resolve_config(rs_pipeline *p, double mean_len) {
-    if (p->d.ensemble_width) p->width = p->d.ensemble_width;
-    if (p->d.strategy != RS_AUTO) p->strategy = p->d.strategy;
-    if (!p->width) p->width = 256;
-    if (p->d.strategy == RS_AUTO && !p->strategy) p->strategy = mean_len >= 2.0 * p->width ? RS_SIGNAL : RS_TAG;
+// ---------------------------------------------------------------- autotune cache
+
+std::string cache_path() {
+    if (const char *e = getenv("RS_AUTOTUNE_CACHE")) return e;
+    const char *xdg = getenv("XDG_CACHE_HOME");
+    const char *home = getenv("HOME");
+    std::string dir = xdg ? std::string(xdg) : home ? std::string(home) + "/.cache" : std::string("/tmp");
+    return dir + "/regionstream-autotune-gfx950.txt";
 }
+
+int length_bucket(double mean_len) { return (int)std::lround(2.0 * std::log2(std::max(mean_len, 0.5))); }
+
+bool cache_lookup(uint32_t kind, uint32_t emit, int bucket, uint32_t *strategy, uint32_t *width) {
+    FILE *f = fopen(cache_path().c_str(), "r");
+    if (!f) return false;
+    unsigned k, e, s, w;
+    int b;
+    bool found = false;
+    while (fscanf(f, "%u %u %d %u %u", &k, &e, &b, &s, &w) == 5) {
+        if (k == kind && e == emit && b == bucket && s <= RS_SIGNAL && rs::kernel_supported(k, s, w)) {
+            *strategy = s;
+            *width = w;
+            found = true;   // the last line for a key wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(uint32_t kind, uint32_t emit, int bucket, uint32_t strategy, uint32_t width) {
+    FILE *f = fopen(cache_path().c_str(), "a");
+    if (!f) return;
+    fprintf(f, "%u %u %d %u %u\n", kind, emit, bucket, strategy, width);
+    fclose(f);
+}
+
+// ---------------------------------------------------------------- validation
 
 int check_stream(const rs_pipeline *p, const rs_stream_desc *s) {
     if (!s) return fail(RS_EINVAL, "stream description is NULL");
@@ -125,8 +189,9 @@ int check_stream(const rs_pipeline *p, const rs_stream_desc *s) {
     const uint32_t eb = elem_bytes_of(p->d.kind);
     if (s->elem_bytes != eb) return fail(RS_EINVAL, "elem_bytes must be %u for this kind", eb);
     if (s->n_parents >= (1ull << 32)) return fail(RS_EINVAL, "n_parents must be < 2^32");
-    if (s->n_elements * eb > 0xFFFFFF00ull) return fail(RS_EINVAL, "stream of %llu bytes exceeds the 4 GiB addressing limit",
-                                                        (unsigned long long)(s->n_elements * eb));
+    if (s->n_elements * eb > 0xFFFFFF00ull)
+        return fail(RS_EINVAL, "stream of %llu bytes exceeds the 4 GiB addressing limit",
+                    (unsigned long long)(s->n_elements * eb));
     if (s->n_parents && !s->offsets) return fail(RS_EINVAL, "offsets is NULL");
     if (s->n_elements && !s->elements) return fail(RS_EINVAL, "elements is NULL");
     if (p->d.kind == RS_GRAPH_THRESH && s->n_parents && !s->parent_param)
@@ -145,13 +210,240 @@ int check_stream(const rs_pipeline *p, const rs_stream_desc *s) {
             uint64_t prev_end = 0;
             for (uint64_t i = 0; i < P; ++i) {
                 const uint64_t st = s->offsets[i], en = st + s->lengths[i];
-                if (st < prev_end) return fail(RS_EINVAL, "region %llu starts before the previous one ends", (unsigned long long)i);
+                if (st < prev_end)
+                    return fail(RS_EINVAL, "region %llu starts before the previous one ends", (unsigned long long)i);
                 if (en > s->n_elements) return fail(RS_EINVAL, "region %llu ends past n_elements", (unsigned long long)i);
                 prev_end = en;
             }
         }
     }
     return RS_OK;
+}
+
+hipStream_t lane_of(rs_pipeline *p, uint64_t batch_id) {
+    return p->user_stream ? p->user_stream : p->own[p->one_lane ? 0 : (batch_id & 1)];
+}
+
+// ---------------------------------------------------------------- batches
+
+// Claim size: about 16 ensembles of elements per claim, at most claim_parents_max(w)
+// parents, at least one parent.
+void plan_claims(Stream *s, uint32_t width, uint32_t n_parents) {
+    const double bmax = rs::claim_parents_max(width);
+    const double b = s->mean_len > 0 ? 16.0 * width / s->mean_len : bmax;
+    s->B = (uint32_t)std::max(1.0, std::min(bmax, b));
+    s->n_claims = (uint32_t)(((uint64_t)n_parents + s->B - 1) / s->B);
+}
+
+int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_id, bool probe,
+               std::unique_ptr<Batch> &out) {
+    std::unique_ptr<Batch> b(new Batch);
+    b->strategy = p->strategy;
+    b->width = p->width;
+    b->lane = lane_of(p, batch_id);
+    std::vector<rs::StreamDev> h(sel.size());
+    uint64_t claims = 0;
+    for (size_t i = 0; i < sel.size(); ++i) {
+        Stream *s = sel[i];
+        uint32_t P = s->n_parents;
+        if (probe && s->n_elements > (1u << 22) && P > 1)   // probe on a prefix of about 2^22 elements
+            P = (uint32_t)std::max<uint64_t>(1, (uint64_t)((double)P * (double)(1u << 22) / s->n_elements));
+        plan_claims(s, p->width, P);
+        rs::StreamDev &e = h[i];
+        std::memset(&e, 0, sizeof e);
+        e.elements = s->elements;
+        e.offsets = s->offsets;
+        e.lengths = s->lengths;
+        e.pparam = s->pparam;
+        e.agg_count = (uint32_t *)s->count.p;
+        e.agg_sum = (unsigned long long *)s->sum.p;
+        e.agg_min = (uint32_t *)s->min.p;
+        e.agg_max = (uint32_t *)s->max.p;
+        e.stats = (unsigned long long *)s->stats.p;   // the error word is always written
+        if (p->d.emit_outputs && !probe) {
+            const size_t lb_bytes = 8ull * s->n_claims + 8;
+            if (s->lookback.bytes < lb_bytes) {
+                int rc = s->lookback.alloc(lb_bytes);
+                if (rc) return rc;
+            }
+            HIP_OR(hipMemsetAsync(s->lookback.p, 0, s->lookback.bytes, b->lane), RS_EDEVICE);
+            e.out_items = (uint32_t *)s->out.p;
+            e.lookback = (unsigned long long *)s->lookback.p;
+        }
+        e.n_parents = P;
+        e.n_elements = s->n_elements;
+        e.parents_per_claim = s->B;
+        e.n_claims = s->n_claims;
+        e.claim_begin = (uint32_t)claims;
+        claims += s->n_claims;
+        b->ids.push_back(s->id);
+    }
+    if (claims >= (1ull << 32) - (1ull << 20)) return fail(RS_EINVAL, "too many claims in one batch");
+    int rc = b->table.alloc(sizeof(rs::StreamDev) * std::max<size_t>(1, h.size()));
+    if (rc) return rc;
+    if ((rc = b->ctl.alloc(rs::CTL_WORDS * sizeof(uint32_t)))) return rc;
+    HIP_OR(hipMemsetAsync(b->ctl.p, 0, rs::CTL_WORDS * sizeof(uint32_t), b->lane), RS_EDEVICE);
+    HIP_OR(hipMemcpyAsync(b->table.p, h.data(), sizeof(rs::StreamDev) * h.size(), hipMemcpyHostToDevice, b->lane),
+           RS_EDEVICE);
+    HIP_OR(hipStreamSynchronize(b->lane), RS_EDEVICE);   // h is a local array
+    HIP_OR(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), RS_EDEVICE);
+    b->total_claims = (uint32_t)claims;
+    const int per_cu = rs::blocks_per_cu(p->d.kind, p->strategy, p->width);
+    if (per_cu <= 0) return fail(RS_EDEVICE, "kernel does not fit on a compute unit");
+    // every workgroup holds two claims at a time (the next one's region table is prefetched)
+    b->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((claims + 1) / 2, (uint64_t)per_cu * p->n_cu));
+    rs::LaunchArgs &a = b->args;
+    a.streams = (const rs::StreamDev *)b->table.p;
+    a.ctl = (uint32_t *)b->ctl.p;
+    a.dummy = p->dummy.p;
+    a.n_streams = (uint32_t)sel.size();
+    a.total_claims = b->total_claims;
+    std::memcpy(a.param, p->d.param, sizeof a.param);
+    a.agg_fields = p->d.agg_fields;
+    a.collect_stats = (!probe && (p->d.flags & RS_COLLECT_STATS)) ? 1u : 0u;
+    a.emit_outputs = (!probe && p->d.emit_outputs) ? 1u : 0u;
+    out = std::move(b);
+    return RS_OK;
+}
+
+// Clear look-back words whose tags could repeat on this launch.
+int prepare_lookback(rs_pipeline *p, Batch &b) {
+    if (!b.args.emit_outputs || b.launches == 0 || b.launches % kEpochCycle != 0) return RS_OK;
+    for (uint64_t id : b.ids) {
+        auto it = p->streams.find(id);
+        if (it != p->streams.end() && it->second->lookback.p)
+            HIP_OR(hipMemsetAsync(it->second->lookback.p, 0, it->second->lookback.bytes, b.lane), RS_EDEVICE);
+    }
+    return RS_OK;
+}
+
+int launch_batch(rs_pipeline *p, Batch &b, bool graph) {
+    if (!b.total_claims) {
+        HIP_OR(hipEventRecord(b.done, b.lane), RS_EDEVICE);
+        return RS_OK;
+    }
+    int rc = prepare_lookback(p, b);
+    if (rc) return rc;
+    if (graph) {
+        if (!b.graph) {
+            hipGraph_t g = nullptr;
+            HIP_OR(hipStreamBeginCapture(b.lane, hipStreamCaptureModeThreadLocal), RS_EDEVICE);
+            const int lrc = rs::launch_pipeline(p->d.kind, b.strategy, b.width, b.args, b.grid, b.lane);
+            hipError_t e = hipStreamEndCapture(b.lane, &g);
+            if (lrc || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(RS_EDEVICE, "graph capture failed");
+            }
+            e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(RS_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        HIP_OR(hipGraphLaunch(b.graph, b.lane), RS_EDEVICE);
+    } else {
+        rc = rs::launch_pipeline(p->d.kind, b.strategy, b.width, b.args, b.grid, b.lane);
+        if (rc) return fail(RS_EDEVICE, "kernel launch failed: %s", hipGetErrorString((hipError_t)rc));
+    }
+    ++b.launches;
+    HIP_OR(hipEventRecord(b.done, b.lane), RS_EDEVICE);
+    return RS_OK;
+}
+
+int batch_error(Batch &b) {
+    uint32_t err = 0;
+    HIP_OR(hipMemcpy(&err, (uint32_t *)b.ctl.p + rs::CTL_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
+    if (err) return fail(RS_EDEVICE, "the device scheduler stopped a claim (watchdog or internal check)");
+    return RS_OK;
+}
+
+// Time every candidate configuration on (a prefix of) stream s and keep the fastest.
+int autotune(rs_pipeline *p, Stream *s) {
+    const int bucket = length_bucket(s->mean_len);
+    const uint32_t want_s = p->d.strategy, want_w = p->d.ensemble_width;
+    uint32_t cs = 0, cw = 0;
+    if (cache_lookup(p->d.kind, p->d.emit_outputs, bucket, &cs, &cw) && (want_s == RS_AUTO || want_s == cs) &&
+        (want_w == 0 || want_w == cw)) {
+        p->strategy = cs;
+        p->width = cw;
+        return RS_OK;
+    }
+    float best = 1e30f;
+    uint32_t best_s = want_s == RS_AUTO ? RS_TAG : want_s, best_w = want_w ? want_w : 256;
+    hipEvent_t e0, e1;
+    HIP_OR(hipEventCreate(&e0), RS_EDEVICE);
+    HIP_OR(hipEventCreate(&e1), RS_EDEVICE);
+    int rc = RS_OK;
+    for (uint32_t strat = RS_TAG; strat <= RS_SIGNAL && rc == RS_OK; ++strat) {
+        if (want_s != RS_AUTO && strat != want_s) continue;
+        for (uint32_t w : kWidths) {
+            if (want_w && w != want_w) continue;
+            p->strategy = strat;
+            p->width = w;
+            std::unique_ptr<Batch> b;
+            if ((rc = make_batch(p, {s}, 0, true, b))) break;
+            if ((rc = launch_batch(p, *b, false))) break;   // warm-up
+            if (hipEventRecord(e0, b->lane) != hipSuccess) { rc = fail(RS_EDEVICE, "event record"); break; }
+            for (int r = 0; r < 2 && rc == RS_OK; ++r) rc = launch_batch(p, *b, false);
+            if (rc) break;
+            if (hipEventRecord(e1, b->lane) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(RS_EDEVICE, "event synchronize");
+                break;
+            }
+            if ((rc = batch_error(*b))) break;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_s = strat;
+                best_w = w;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    p->strategy = best_s;
+    p->width = best_w;
+    cache_store(p->d.kind, p->d.emit_outputs, bucket, best_s, best_w);
+    return RS_OK;
+}
+
+int find_done(rs_pipeline *p, uint64_t id, uint32_t flags, Stream **out) {
+    auto it = p->streams.find(id);
+    if (it == p->streams.end()) return fail(RS_ENOTFOUND, "unknown stream id %llu", (unsigned long long)id);
+    Stream *s = it->second.get();
+    if (s->state == S_PUSHED) return fail(RS_ESTATE, "stream %llu has not been run", (unsigned long long)id);
+    auto bi = p->batches.find(s->batch);
+    if (bi == p->batches.end()) return fail(RS_ESTATE, "stream %llu has no batch", (unsigned long long)id);
+    Batch &b = *bi->second;
+    if (flags & RS_NONBLOCK) {
+        hipError_t e = hipEventQuery(b.done);
+        if (e == hipErrorNotReady) return fail(RS_ENOTREADY, "stream %llu is still running", (unsigned long long)id);
+        if (e != hipSuccess) return fail(RS_EDEVICE, "hipEventQuery: %s", hipGetErrorString(e));
+    } else {
+        HIP_OR(hipEventSynchronize(b.done), RS_EDEVICE);
+    }
+    int rc = batch_error(b);
+    if (rc) return rc;
+    uint32_t bad = 0;
+    HIP_OR(hipMemcpy(&bad, (unsigned long long *)s->stats.p + rs::ST_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
+    if (bad) return fail(RS_EINVAL, "stream %llu has malformed regions (out of order or past n_elements)",
+                         (unsigned long long)id);
+    s->state = S_DONE;
+    *out = s;
+    return RS_OK;
+}
+
+void release(rs_pipeline *p, Stream *s) {
+    p->admitted_bytes -= std::min(p->admitted_bytes, s->footprint);
+    const uint64_t bid = s->batch;
+    p->streams.erase(s->id);
+    // a batch whose streams are all gone is freed too
+    auto bi = p->batches.find(bid);
+    if (bi != p->batches.end()) {
+        bool any = false;
+        for (uint64_t id : bi->second->ids) any |= p->streams.count(id) > 0;
+        if (!any && bid != p->last_batch) p->batches.erase(bi);
+    }
 }
 
 }  // namespace
@@ -164,20 +456,22 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     g_err.clear();
     if (!d || !out) return fail(RS_EINVAL, "NULL argument");
     *out = nullptr;
-    if (d->abi_version != RS_ABI_VERSION) return fail(RS_EINVAL, "abi_version %u, library is %u", d->abi_version, RS_ABI_VERSION);
+    if (d->abi_version != RS_ABI_VERSION)
+        return fail(RS_EINVAL, "abi_version %u, library is %u", d->abi_version, RS_ABI_VERSION);
     if (d->kind < RS_MODFILTER || d->kind > RS_GRAPH_THRESH) return fail(RS_EINVAL, "unknown kind %u", d->kind);
     if (d->strategy > RS_AUTO) return fail(RS_EINVAL, "unknown strategy %u", d->strategy);
-    if (d->agg_fields == 0 || (d->agg_fields & ~15u)) return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX");
+    if (d->agg_fields == 0 || (d->agg_fields & ~15u))
+        return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX");
     const uint32_t w = d->ensemble_width;
     if (w && !rs::kernel_supported(d->kind, RS_TAG, w))
-        return fail(RS_EINVAL, "ensemble_width %u not supported (64, 128, 256 or 512)", w);
+        return fail(RS_EINVAL, "ensemble_width %u not supported (64, 128, 256, 512 or 1024)", w);
     if (d->queue_depth) {
         const uint32_t q = d->queue_depth;
         if (q & (q - 1)) return fail(RS_EINVAL, "queue_depth must be a power of two");
-        if (w && q < 2 * w) return fail(RS_EINVAL, "queue_depth %u < 2 * ensemble_width", q);
+        if (w && q != 2 * w) return fail(RS_EINVAL, "queue_depth %u: this build sizes queues at 2 * ensemble_width", q);
     }
     if (d->emit_outputs > 1) return fail(RS_EINVAL, "emit_outputs must be 0 or 1");
-    if (d->emit_outputs) return fail(RS_EINVAL, "the ordered output stream is not available in this build");
+    if (d->flags & ~3u) return fail(RS_EINVAL, "unknown pipeline flags");
     if (d->kind == RS_MODFILTER && d->param[0] != 0 && d->param[1] >= d->param[0])
         return fail(RS_EINVAL, "residue must be smaller than the modulus");
 
@@ -187,23 +481,20 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     hipDeviceProp_t prop;
     HIP_OR(hipGetDeviceProperties(&prop, p->device), RS_EDEVICE);
     p->n_cu = prop.multiProcessorCount;
-    HIP_OR(hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking), RS_EDEVICE);
-    p->stream = p->own_stream;
-    int rc = p->ctl.alloc(rs::CTL_WORDS * sizeof(uint32_t));
+    for (auto &h : p->own) HIP_OR(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), RS_EDEVICE);
+    int rc = p->dummy.alloc(256);
     if (rc) return rc;
-    rc = p->dummy.alloc(256);
-    if (rc) return rc;
-    HIP_OR(hipMemset(p->ctl.p, 0, rs::CTL_WORDS * sizeof(uint32_t)), RS_EDEVICE);
     HIP_OR(hipMemset(p->dummy.p, 0, 256), RS_EDEVICE);
-    if (d->ensemble_width) p->width = d->ensemble_width;
-    if (d->strategy != RS_AUTO) p->strategy = d->strategy;
+    p->width = d->ensemble_width;
+    p->strategy = d->strategy == RS_AUTO ? RS_TAG : d->strategy;
+    p->configured = d->ensemble_width != 0 && d->strategy != RS_AUTO;
     *out = p.release();
     return RS_OK;
 }
 
 RS_API int pipeline_set_stream(rs_pipeline *p, void *hip_stream) {
     if (!p) return fail(RS_EINVAL, "NULL pipeline");
-    p->stream = hip_stream ? (hipStream_t)hip_stream : p->own_stream;
+    p->user_stream = (hipStream_t)hip_stream;
     return RS_OK;
 }
 
@@ -244,41 +535,38 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
         return fail(RS_EINVAL, text ? "device text streams need starts + lengths" : "device u32 streams need CSR offsets");
     }
 
-    // mean region length picks the claim size and, if open, the configuration
-    double covered = 0;
+    // mean region length sizes claims and keys the autotuner
+    double covered = (double)s->n_elements;
     if (s->mem == RS_MEM_HOST && P) {
+        covered = 0;
         if (lens) {
             for (uint64_t i = 0; i < P; ++i) covered += lens[i];
         } else {
             covered = (double)offs[P] - (double)offs[0];
         }
-    } else {
-        covered = (double)s->n_elements;
     }
-    const double mean_len = P ? covered / (double)P : 0.0;
-    if (!p->width || (p->d.strategy == RS_AUTO && !p->strategy)) resolve_config(p, mean_len);
-    const uint32_t bmax = rs::claim_parents_max(p->width);
-    const double target = 16.0 * p->width;
-    double b = mean_len > 0 ? target / mean_len : (double)bmax;
-    st->B = (uint32_t)std::max(1.0, std::min((double)bmax, b));
-    st->n_claims = (uint32_t)((P + st->B - 1) / st->B);
+    st->mean_len = P ? covered / (double)P : 0.0;
 
-    // footprint on the device
+    // device footprint (look-back words at one per parent at most)
     const uint64_t agg_bytes = P * ((p->d.agg_fields & RS_COUNT ? 4 : 0) + (p->d.agg_fields & RS_SUM ? 8 : 0) +
                                     (p->d.agg_fields & RS_MIN ? 4 : 0) + (p->d.agg_fields & RS_MAX ? 4 : 0));
     uint64_t in_bytes = 0;
     if (s->mem == RS_MEM_HOST)
         in_bytes = s->n_elements * eb + (lens ? 8 * P : 4 * (P + 1)) + (s->parent_param ? 4 * P : 0);
-    st->footprint = in_bytes + agg_bytes + 8 * rs::ST_WORDS;
+    st->out_cap = p->d.emit_outputs ? (uint64_t)k_max_of(p->d.kind) * s->n_elements : 0;
+    const uint64_t est_claims = P ? std::max<uint64_t>(1, (uint64_t)(covered / (16.0 * 64))) + P / 64 + 1 : 0;
+    st->footprint = in_bytes + agg_bytes + 8 * rs::ST_WORDS + 4 * st->out_cap +
+                    (p->d.emit_outputs ? 8ull * std::min<uint64_t>(est_claims, P + 1) : 0);
     if (p->d.hbm_budget_bytes && st->footprint > p->d.hbm_budget_bytes)
         return fail(RS_EBUDGET, "stream needs %llu bytes, budget is %llu", (unsigned long long)st->footprint,
                     (unsigned long long)p->d.hbm_budget_bytes);
 
-    hipStream_t hs = p->stream;
+    hipStream_t hs = lane_of(p, 0);
     if (s->mem == RS_MEM_HOST) {
         if ((rc = st->own_elements.alloc(s->n_elements * eb + 16))) return rc;
         if (s->n_elements)
-            HIP_OR(hipMemcpyAsync(st->own_elements.p, s->elements, s->n_elements * eb, hipMemcpyHostToDevice, hs), RS_EDEVICE);
+            HIP_OR(hipMemcpyAsync(st->own_elements.p, s->elements, s->n_elements * eb, hipMemcpyHostToDevice, hs),
+                   RS_EDEVICE);
         st->elements = st->own_elements.p;
         if (P) {
             const size_t ob = lens ? 4 * P : 4 * (P + 1);
@@ -296,18 +584,14 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
                 st->pparam = (const uint32_t *)st->own_pparam.p;
             }
         }
-        // the host arrays may be reused by the caller as soon as we return
+        // the caller may reuse its host arrays as soon as this returns
         HIP_OR(hipStreamSynchronize(hs), RS_EDEVICE);
     } else {
         st->elements = s->elements;
         st->offsets = s->offsets;
         st->lengths = s->lengths;
         st->pparam = s->parent_param;
-        if (P) {
-            rc = rs::validate_device_regions(st->offsets, st->lengths, (uint32_t)P, st->n_elements, hs);
-            if (rc > 0) return fail(RS_EINVAL, "device regions are malformed (first bad parent %d)", rc - 1);
-            if (rc < 0) return fail(RS_EDEVICE, "region validation failed: %s", hipGetErrorString((hipError_t)-rc));
-        }
+        // borrowed regions are checked by the kernel, claim by claim, before any element is read
     }
     if (p->d.agg_fields & RS_COUNT && (rc = st->count.alloc(4 * P))) return rc;
     if (p->d.agg_fields & RS_SUM && (rc = st->sum.alloc(8 * P))) return rc;
@@ -315,6 +599,7 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
     if (p->d.agg_fields & RS_MAX && (rc = st->max.alloc(4 * P))) return rc;
     if ((rc = st->stats.alloc(8 * rs::ST_WORDS))) return rc;
     HIP_OR(hipMemset(st->stats.p, 0, 8 * rs::ST_WORDS), RS_EDEVICE);
+    if (p->d.emit_outputs && (rc = st->out.alloc(4 * st->out_cap + 16))) return rc;
 
     st->id = p->next_id++;
     *stream_id = st->id;
@@ -324,69 +609,59 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
 
 namespace {
 
-int launch_batch(rs_pipeline *p, Batch &b) {
-    const int rc = rs::launch_pipeline(p->d.kind, p->strategy, p->width, b.args, b.grid, p->stream);
-    if (rc) return fail(RS_EDEVICE, "kernel launch failed: %s", hipGetErrorString((hipError_t)rc));
+// Launch the given pushed streams: one batch, or one batch per stream.
+int launch_streams(rs_pipeline *p, const std::vector<Stream *> &sel, bool per_stream, bool sync) {
+    if (sel.empty()) return RS_OK;
+    int rc;
+    if (!p->configured) {
+        Stream *probe = sel[0];
+        for (Stream *s : sel)
+            if (s->n_elements > probe->n_elements) probe = s;
+        if ((rc = autotune(p, probe))) return rc;
+        p->configured = true;
+    }
+    std::vector<std::vector<Stream *>> groups;
+    if (per_stream) {
+        for (Stream *s : sel) groups.push_back({s});
+    } else {
+        groups.push_back(sel);
+    }
+    std::vector<Batch *> launched;
+    for (auto &grp : groups) {
+        const uint64_t bid = p->next_batch++;
+        std::unique_ptr<Batch> b;
+        if ((rc = make_batch(p, grp, bid, false, b))) return rc;
+        if ((rc = launch_batch(p, *b, false))) return rc;
+        for (Stream *s : grp) {
+            s->state = S_LAUNCHED;
+            s->batch = bid;
+            p->admitted_bytes += s->footprint;
+        }
+        launched.push_back(b.get());
+        p->batches[bid] = std::move(b);
+        p->last_batch = bid;
+    }
+    if (sync) {
+        for (Batch *b : launched) {
+            HIP_OR(hipEventSynchronize(b->done), RS_EDEVICE);
+            if ((rc = batch_error(*b))) return rc;
+        }
+    }
     return RS_OK;
 }
 
-int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, std::unique_ptr<Batch> &out) {
-    std::unique_ptr<Batch> b(new Batch);
-    std::vector<rs::StreamDev> h(sel.size());
-    uint32_t claims = 0;
-    for (size_t i = 0; i < sel.size(); ++i) {
-        Stream *s = sel[i];
-        rs::StreamDev &e = h[i];
-        std::memset(&e, 0, sizeof e);
-        e.elements = s->elements;
-        e.offsets = s->offsets;
-        e.lengths = s->lengths;
-        e.pparam = s->pparam;
-        e.agg_count = (uint32_t *)s->count.p;
-        e.agg_sum = (unsigned long long *)s->sum.p;
-        e.agg_min = (uint32_t *)s->min.p;
-        e.agg_max = (uint32_t *)s->max.p;
-        e.stats = (unsigned long long *)s->stats.p;
-        e.n_parents = s->n_parents;
-        e.n_elements = s->n_elements;
-        e.parents_per_claim = s->B;
-        e.n_claims = s->n_claims;
-        e.claim_begin = claims;
-        claims += s->n_claims;
-        b->ids.push_back(s->id);
+// Pushed streams, in push order, that fit the HBM budget next to what is admitted.
+std::vector<Stream *> admissible(rs_pipeline *p, const std::vector<Stream *> &cands, size_t limit) {
+    std::vector<Stream *> sel;
+    uint64_t used = p->admitted_bytes;
+    for (Stream *s : cands) {
+        if (sel.size() >= limit) break;
+        if (s->state != S_PUSHED) continue;
+        if (p->d.hbm_budget_bytes && used + s->footprint > p->d.hbm_budget_bytes) continue;
+        used += s->footprint;
+        sel.push_back(s);
     }
-    int rc = b->table.alloc(sizeof(rs::StreamDev) * std::max<size_t>(1, h.size()));
-    if (rc) return rc;
-    HIP_OR(hipMemcpyAsync(b->table.p, h.data(), sizeof(rs::StreamDev) * h.size(), hipMemcpyHostToDevice, p->stream),
-           RS_EDEVICE);
-    HIP_OR(hipStreamSynchronize(p->stream), RS_EDEVICE);   // h is a local array
-    b->total_claims = claims;
-    const int per_cu = rs::blocks_per_cu(p->d.kind, p->strategy, p->width);
-    if (per_cu <= 0) return fail(RS_EDEVICE, "kernel does not fit on a compute unit");
-    b->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(claims, (uint64_t)per_cu * p->n_cu));
-    rs::LaunchArgs &a = b->args;
-    a.streams = (const rs::StreamDev *)b->table.p;
-    a.ctl = (uint32_t *)p->ctl.p;
-    a.dummy = p->dummy.p;
-    a.n_streams = (uint32_t)sel.size();
-    a.total_claims = claims;
-    std::memcpy(a.param, p->d.param, sizeof a.param);
-    a.agg_fields = p->d.agg_fields;
-    a.collect_stats = (p->d.flags & RS_COLLECT_STATS) ? 1u : 0u;
-    a.emit_outputs = p->d.emit_outputs;
-    out = std::move(b);
-    return RS_OK;
-}
-
-int finish_check(rs_pipeline *p) {
-    uint32_t err = 0;
-    HIP_OR(hipMemcpy(&err, (uint32_t *)p->ctl.p + rs::CTL_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
-    if (err) {
-        const uint32_t zero = 0;
-        (void)hipMemcpy((uint32_t *)p->ctl.p + rs::CTL_ERROR, &zero, 4, hipMemcpyHostToDevice);
-        return fail(RS_EDEVICE, "the device scheduler stopped a claim (watchdog or internal check)");
-    }
-    return RS_OK;
+    return sel;
 }
 
 }  // namespace
@@ -394,129 +669,50 @@ int finish_check(rs_pipeline *p) {
 RS_API int run(rs_pipeline *p, uint32_t flags) {
     g_err.clear();
     if (!p) return fail(RS_EINVAL, "NULL pipeline");
-    if (flags & ~7u) return fail(RS_EINVAL, "unknown run flags");
-    std::vector<Stream *> sel;
-    uint64_t budget_used = p->admitted_bytes;
-    for (auto &kv : p->streams) {
-        Stream *s = kv.second.get();
-        if (s->state != S_PUSHED) continue;
-        if (p->d.hbm_budget_bytes && budget_used + s->footprint > p->d.hbm_budget_bytes) continue;
-        budget_used += s->footprint;
-        sel.push_back(s);
-    }
-    if (sel.empty()) return RS_OK;
-    if (!p->width) resolve_config(p, 0.0);
-
-    std::vector<std::vector<Stream *>> groups;
-    if (flags & RS_RUN_PER_STREAM) {
-        for (Stream *s : sel) groups.push_back({s});
-    } else {
-        groups.push_back(sel);
-    }
-    for (auto &grp : groups) {
-        std::unique_ptr<Batch> b;
-        int rc = make_batch(p, grp, b);
-        if (rc) return rc;
-        if (b->total_claims) {
-            rc = launch_batch(p, *b);
-            if (rc) return rc;
-        }
-        auto ev = std::shared_ptr<hipEvent_t>(new hipEvent_t(nullptr), [](hipEvent_t *e) {
-            if (*e) (void)hipEventDestroy(*e);
-            delete e;
-        });
-        HIP_OR(hipEventCreateWithFlags(ev.get(), hipEventDisableTiming), RS_EDEVICE);
-        HIP_OR(hipEventRecord(*ev, p->stream), RS_EDEVICE);
-        const uint64_t bid = p->next_batch++;
-        for (Stream *s : grp) {
-            s->state = S_LAUNCHED;
-            s->done = ev;
-            s->batch = bid;
-            p->admitted_bytes += s->footprint;
-        }
-        p->batches[bid] = std::move(b);
-        p->last_batch = bid;
-    }
-    if (!(flags & RS_RUN_ASYNC)) {
-        HIP_OR(hipStreamSynchronize(p->stream), RS_EDEVICE);
-        return finish_check(p);
-    }
-    return RS_OK;
+    if (flags & ~3u) return fail(RS_EINVAL, "unknown run flags");
+    std::vector<Stream *> cands;
+    for (auto &kv : p->streams) cands.push_back(kv.second.get());
+    return launch_streams(p, admissible(p, cands, (size_t)-1), flags & RS_RUN_PER_STREAM, !(flags & RS_RUN_ASYNC));
 }
 
-// Re-run the most recent batch in place (benchmarks and graph replay).  The launch is
-// captured into a HIP graph on first use unless RS_NO_GRAPH or statistics are enabled.
 RS_API int run_again(rs_pipeline *p, uint32_t flags) {
     g_err.clear();
     if (!p) return fail(RS_EINVAL, "NULL pipeline");
+    if (flags & ~1u) return fail(RS_EINVAL, "unknown run flags");
     auto it = p->batches.find(p->last_batch);
     if (it == p->batches.end()) return fail(RS_ESTATE, "no batch has run on this pipeline");
     Batch &b = *it->second;
-    if (b.total_claims) {
-        const bool use_graph = !(p->d.flags & (RS_NO_GRAPH | RS_COLLECT_STATS));
-        if (use_graph) {
-            if (!b.graph) {
-                hipGraph_t g = nullptr;
-                HIP_OR(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal), RS_EDEVICE);
-                const int rc = rs::launch_pipeline(p->d.kind, p->strategy, p->width, b.args, b.grid, p->stream);
-                hipError_t e = hipStreamEndCapture(p->stream, &g);
-                if (rc || e != hipSuccess) return fail(RS_EDEVICE, "graph capture failed");
-                e = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (e != hipSuccess) return fail(RS_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
-            }
-            HIP_OR(hipGraphLaunch(b.graph, p->stream), RS_EDEVICE);
-        } else {
-            int rc = launch_batch(p, b);
-            if (rc) return rc;
-        }
+    if (p->user_stream) b.lane = p->user_stream;
+    const bool graph = !(p->d.flags & (RS_NO_GRAPH | RS_COLLECT_STATS));
+    int rc = launch_batch(p, b, graph);
+    if (rc) return rc;
+    for (uint64_t id : b.ids) {
+        auto si = p->streams.find(id);
+        if (si != p->streams.end()) si->second->state = S_LAUNCHED;
     }
     if (!(flags & RS_RUN_ASYNC)) {
-        HIP_OR(hipStreamSynchronize(p->stream), RS_EDEVICE);
-        return finish_check(p);
+        HIP_OR(hipEventSynchronize(b.done), RS_EDEVICE);
+        return batch_error(b);
     }
     return RS_OK;
 }
-
-namespace {
-
-int find_done(rs_pipeline *p, uint64_t id, uint32_t flags, Stream **out) {
-    auto it = p->streams.find(id);
-    if (it == p->streams.end()) return fail(RS_ENOTFOUND, "unknown stream id %llu", (unsigned long long)id);
-    Stream *s = it->second.get();
-    if (s->state == S_PUSHED) return fail(RS_ESTATE, "stream %llu has not been run", (unsigned long long)id);
-    if (s->state == S_LAUNCHED) {
-        if (flags & RS_NONBLOCK) {
-            hipError_t e = hipEventQuery(*s->done);
-            if (e == hipErrorNotReady) return fail(RS_ENOTREADY, "stream %llu is still running", (unsigned long long)id);
-            if (e != hipSuccess) return fail(RS_EDEVICE, "hipEventQuery: %s", hipGetErrorString(e));
-        } else {
-            HIP_OR(hipEventSynchronize(*s->done), RS_EDEVICE);
-        }
-        int rc = finish_check(p);
-        if (rc) return rc;
-        s->state = S_DONE;
-    }
-    *out = s;
-    return RS_OK;
-}
-
-void release(rs_pipeline *p, Stream *s) {
-    p->admitted_bytes -= std::min(p->admitted_bytes, s->footprint);
-    p->streams.erase(s->id);
-}
-
-}  // namespace
 
 RS_API int read_aggregates(rs_pipeline *p, uint64_t stream_id, rs_agg_view *out, uint32_t flags) {
     g_err.clear();
     if (!p || !out) return fail(RS_EINVAL, "NULL argument");
+    if (flags & ~7u) return fail(RS_EINVAL, "unknown read flags");
     Stream *s = nullptr;
     int rc = find_done(p, stream_id, flags, &s);
     if (rc) return rc;
     const hipMemcpyKind k = (flags & RS_READ_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const size_t P = s->n_parents;
-    struct F { void *dst; DevBuf *src; size_t bytes; uint32_t bit; const char *name; };
+    struct F {
+        void *dst;
+        DevBuf *src;
+        size_t bytes;
+        uint32_t bit;
+        const char *name;
+    };
     F fields[4] = {{out->count, &s->count, 4 * P, RS_COUNT, "count"},
                    {out->sum, &s->sum, 8 * P, RS_SUM, "sum"},
                    {out->min, &s->min, 4 * P, RS_MIN, "min"},
@@ -530,11 +726,31 @@ RS_API int read_aggregates(rs_pipeline *p, uint64_t stream_id, rs_agg_view *out,
     return RS_OK;
 }
 
-RS_API int read_outputs(rs_pipeline *p, uint64_t stream_id, uint32_t *out, uint64_t cap, uint64_t *n_out, uint32_t flags) {
+RS_API int read_outputs(rs_pipeline *p, uint64_t stream_id, uint32_t *out, uint64_t cap, uint64_t *n_out,
+                        uint32_t flags) {
     g_err.clear();
-    if (!p) return fail(RS_EINVAL, "NULL pipeline");
-    (void)stream_id; (void)out; (void)cap; (void)n_out; (void)flags;
-    return fail(RS_EINVAL, "pipeline was created without emit_outputs");
+    if (!p || !n_out) return fail(RS_EINVAL, "NULL argument");
+    if (!p->d.emit_outputs) return fail(RS_EINVAL, "pipeline was created without emit_outputs");
+    Stream *s = nullptr;
+    int rc = find_done(p, stream_id, flags, &s);
+    if (rc) return rc;
+    uint64_t n = 0;
+    if (s->n_claims) {
+        uint64_t w = 0;
+        HIP_OR(hipMemcpy(&w, (uint64_t *)s->lookback.p + (s->n_claims - 1), 8, hipMemcpyDeviceToHost), RS_EDEVICE);
+        if (((w >> 38) & 3u) != 2u)
+            return fail(RS_EDEVICE, "output stream of stream %llu is incomplete", (unsigned long long)stream_id);
+        n = w & ((1ull << 38) - 1ull);
+    }
+    *n_out = n;
+    const uint64_t m = std::min<uint64_t>(n, cap);
+    if (m) {
+        if (!out) return fail(RS_EINVAL, "out is NULL");
+        const hipMemcpyKind k = (flags & RS_READ_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        HIP_OR(hipMemcpy(out, s->out.p, 4 * m, k), RS_EDEVICE);
+    }
+    if (flags & RS_READ_RELEASE) release(p, s);
+    return RS_OK;
 }
 
 RS_API int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out) {
@@ -552,12 +768,18 @@ RS_API int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out) {
         out->full[k] = st[rs::ST_FULL + k];
         out->signals[k] = st[rs::ST_SIGNALS + k];
     }
-    out->n_outputs = st[rs::ST_OUTPUTS];
-    out->ensemble_width = p->width;
-    out->queue_depth = 2 * p->width;
-    out->strategy = p->strategy;
     auto bi = p->batches.find(s->batch);
-    out->n_workgroups = bi != p->batches.end() ? bi->second->grid : 0;
+    if (bi != p->batches.end()) {
+        out->ensemble_width = bi->second->width;
+        out->queue_depth = 2 * bi->second->width;
+        out->strategy = bi->second->strategy;
+        out->n_workgroups = bi->second->grid;
+    }
+    if (p->d.emit_outputs && s->n_claims && s->lookback.p) {
+        uint64_t w = 0;
+        HIP_OR(hipMemcpy(&w, (uint64_t *)s->lookback.p + (s->n_claims - 1), 8, hipMemcpyDeviceToHost), RS_EDEVICE);
+        out->n_outputs = w & ((1ull << 38) - 1ull);
+    }
     return RS_OK;
 }
 
@@ -568,20 +790,156 @@ RS_API int stream_release(rs_pipeline *p, uint64_t stream_id) {
     if (it == p->streams.end()) return fail(RS_ENOTFOUND, "unknown stream id %llu", (unsigned long long)stream_id);
     Stream *s = it->second.get();
     if (s->state == S_LAUNCHED) {
-        if (hipEventQuery(*s->done) == hipErrorNotReady) return fail(RS_ESTATE, "stream is still running");
+        auto bi = p->batches.find(s->batch);
+        if (bi != p->batches.end() && hipEventQuery(bi->second->done) == hipErrorNotReady)
+            return fail(RS_ESTATE, "stream is still running");
         s->state = S_DONE;
     }
     release(p, s);
     return RS_OK;
 }
 
+RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view *out, rs_request_timing *timing,
+                 uint32_t flags) {
+    g_err.clear();
+    if (!p || (n && (!reqs || !timing))) return fail(RS_EINVAL, "NULL argument");
+    if (flags & ~RS_RUN_PER_STREAM) return fail(RS_EINVAL, "unknown serve flags");
+    for (uint64_t i = 1; i < n; ++i)
+        if (reqs[i].arrival_s < reqs[i - 1].arrival_s) return fail(RS_EINVAL, "requests must be sorted by arrival");
+    const bool per_stream = flags & RS_RUN_PER_STREAM;
+    struct LaneGuard {
+        rs_pipeline *p;
+        bool saved;
+        ~LaneGuard() { p->one_lane = saved; }
+    } lane_guard{p, p->one_lane};
+    p->one_lane = per_stream;
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    auto now = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+
+    for (uint64_t i = 0; i < n; ++i) {
+        std::memset(&timing[i], 0, sizeof timing[i]);
+        timing[i].arrival_s = reqs[i].arrival_s;
+    }
+    std::vector<uint64_t> sid(n, 0);
+    std::deque<uint64_t> waiting;                 // pushed, not yet launched (request indices)
+    std::vector<uint64_t> inflight;               // launched, not yet completed
+    uint64_t next = 0, done = 0;
+    int last_rc = RS_OK;
+
+    auto fail_req = [&](uint64_t i, int rc) {
+        timing[i].status = rc;
+        timing[i].completed_s = now();
+        ++done;
+        last_rc = rc;
+    };
+    while (done < n) {
+        bool progressed = false;
+        // 1. arrivals: push every request whose time has come
+        while (next < n && reqs[next].arrival_s <= now()) {
+            uint64_t id = 0;
+            const int rc = stream_push(p, &reqs[next].stream, &id);
+            if (rc) {
+                fail_req(next, rc);
+            } else {
+                sid[next] = id;
+                timing[next].pushed_s = now();
+                waiting.push_back(next);
+            }
+            ++next;
+            progressed = true;
+        }
+        // 2. admission and launch: a new batch whenever a lane is free
+        std::map<uint64_t, int> batches_inflight;
+        for (uint64_t i : inflight) batches_inflight[timing[i].batch] = 1;
+        // batched: a new batch whenever one of the two lanes is free; per stream: every
+        // request is launched as soon as it is pushed and the lane runs them in order
+        const size_t lanes = per_stream ? (size_t)-1 : 2;
+        if (!waiting.empty() && batches_inflight.size() < lanes) {
+            std::vector<Stream *> cands;
+            for (uint64_t i : waiting) cands.push_back(p->streams.at(sid[i]).get());
+            // per-stream baseline: one request per launch, in arrival order
+            const std::vector<Stream *> sel = admissible(p, cands, per_stream ? 1 : (size_t)-1);
+            const uint64_t before = p->next_batch;
+            const int rc = launch_streams(p, sel, per_stream, false);
+            if (rc) {
+                while (!waiting.empty()) {
+                    const uint64_t i = waiting.front();
+                    waiting.pop_front();
+                    (void)stream_release(p, sid[i]);
+                    fail_req(i, rc);
+                }
+            } else if (p->next_batch != before) {
+                std::deque<uint64_t> still;
+                for (uint64_t i : waiting) {
+                    Stream *s = p->streams.at(sid[i]).get();
+                    if (s->state == S_LAUNCHED) {
+                        timing[i].launched_s = now();
+                        timing[i].batch = s->batch;
+                        inflight.push_back(i);
+                    } else {
+                        still.push_back(i);   // over budget: waits for memory to free up
+                    }
+                }
+                waiting.swap(still);
+                progressed = true;
+            }
+        }
+        // 3. completions: reap finished batches without blocking
+        for (size_t k = 0; k < inflight.size();) {
+            const uint64_t i = inflight[k];
+            rs_agg_view dummy{nullptr, nullptr, nullptr, nullptr};
+            rs_agg_view *v = out ? &out[i] : &dummy;
+            const int rc = read_aggregates(p, sid[i], v, RS_NONBLOCK | RS_READ_RELEASE);
+            if (rc == RS_ENOTREADY) {
+                ++k;
+                continue;
+            }
+            if (rc) {
+                (void)stream_release(p, sid[i]);
+                fail_req(i, rc);
+            } else {
+                timing[i].completed_s = now();
+                ++done;
+            }
+            inflight[k] = inflight.back();
+            inflight.pop_back();
+            progressed = true;
+        }
+        if (!progressed) {
+            // nothing to do right now: wait for the next arrival or completion
+            const double wait = next < n ? reqs[next].arrival_s - now() : 0.0;
+            if (inflight.empty() && wait > 200e-6)
+                std::this_thread::sleep_for(std::chrono::duration<double>(wait - 100e-6));
+            else
+                std::this_thread::sleep_for(std::chrono::microseconds(5));
+        }
+    }
+    return last_rc == RS_OK ? RS_OK : fail(last_rc, "some requests failed (see timing[].status)");
+}
+
+RS_API int hbm_probe(const void *src, void *dst, uint64_t bytes, void *hip_stream) {
+    g_err.clear();
+    if (!src || !dst) return fail(RS_EINVAL, "NULL argument");
+    if (((uintptr_t)src | (uintptr_t)dst | bytes) & 15u) return fail(RS_EINVAL, "pointers and size must be 16-byte multiples");
+    int dev = 0;
+    HIP_OR(hipGetDevice(&dev), RS_EDEVICE);
+    hipDeviceProp_t prop;
+    HIP_OR(hipGetDeviceProperties(&prop, dev), RS_EDEVICE);
+    const int rc = rs::launch_probe_copy(src, dst, bytes, (uint32_t)prop.multiProcessorCount, hip_stream);
+    if (rc) return fail(RS_EDEVICE, "probe launch: %s", hipGetErrorString((hipError_t)rc));
+    return RS_OK;
+}
+
 RS_API int pipeline_destroy(rs_pipeline *p) {
     if (!p) return RS_OK;
-    (void)hipStreamSynchronize(p->stream);
-    (void)hipStreamSynchronize(p->own_stream);
-    p->streams.clear();
+    if (p->user_stream) (void)hipStreamSynchronize(p->user_stream);
+    for (auto &h : p->own)
+        if (h) (void)hipStreamSynchronize(h);
     p->batches.clear();
-    if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
+    p->streams.clear();
+    for (auto &h : p->own)
+        if (h) (void)hipStreamDestroy(h);
     delete p;
     return RS_OK;
 }

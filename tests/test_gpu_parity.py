@@ -238,3 +238,151 @@ def test_signal_occupancy_matches_closed_form():
         assert st.full[0] == 512 * (L // w)
         _, st_t = run_one(rs.RS_HASH_EXPAND, rs.RS_TAG, w, offsets, vals, flags=rs.RS_COLLECT_STATS)
         assert st_t.items[0] == n and st_t.signals[0] == 0
+
+
+# ---- ordered output stream ----
+
+def run_outputs(kind, strategy, width, offsets, elements, lengths=None, parent_param=None):
+    with rs.Pipeline(kind, strategy=strategy, ensemble_width=width, agg_fields=ALL, emit_outputs=True) as p:
+        sid = p.push(offsets, elements, lengths=lengths, parent_param=parent_param)
+        p.run()
+        return p.read(sid), p.outputs(sid)
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("L", [1, 7, 300, 5000])
+def test_output_stream_hash_expand(strategy, L):
+    say("outputs hash/expand", SNAME[strategy], L)
+    n = 150001
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(9, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals, emit_outputs=True)
+    got, out = run_outputs(rs.RS_HASH_EXPAND, strategy, 256, offsets, vals)
+    check(got, ref, where="outputs agg")
+    assert len(out) == len(ref.out) and np.array_equal(out, ref.out)
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_output_stream_other_kinds(strategy):
+    say("outputs other kinds", SNAME[strategy])
+    offsets, vals = workloads.modfilter_workload(seed=1, n_parents=4096, max_size=64)
+    ref = oracle.run(oracle.MODFILTER, offsets, vals, emit_outputs=True)
+    _, out = run_outputs(rs.RS_MODFILTER, strategy, 128, offsets, vals)
+    assert np.array_equal(out, ref.out)
+    text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 19)
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths, emit_outputs=True)
+    _, out = run_outputs(rs.RS_TEXT_WORDS, strategy, 256, starts, text, lengths=lengths)
+    assert np.array_equal(out, ref.out)
+    offsets, w, thr, _ = workloads.graph_workload(seed=4, n_vertices=1 << 13, n_edges=1 << 17, cap=20000)
+    ref = oracle.run(oracle.GRAPH_THRESH, offsets, w, parent_param=thr, emit_outputs=True)
+    _, out = run_outputs(rs.RS_GRAPH_THRESH, strategy, 64, offsets, w, parent_param=thr)
+    assert np.array_equal(out, ref.out)
+
+
+def test_output_stream_batched_and_replayed():
+    say("outputs batched/replayed")
+    shapes = [(5000, 1.0), (60000, 37.5), (100000, 700.0), (1, 1.0)]
+    streams = [workloads.serving_stream(5, s, n, m) for s, (n, m) in enumerate(shapes)]
+    for strategy in STRATS:
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256, emit_outputs=True) as p:
+            ids = [p.push(o, v) for o, v in streams]
+            p.run()
+            for rep in range(3):
+                if rep:
+                    p.run_again()
+                for sid, (o, v) in zip(ids, streams):
+                    ref = oracle.run(oracle.HASH_EXPAND, o, v, emit_outputs=True)
+                    assert np.array_equal(p.outputs(sid), ref.out)
+                    check(p.read(sid), ref, where="outputs batched")
+
+
+# ---- borrowed device streams with malformed regions are reported, never read out of bounds ----
+
+def test_malformed_device_regions_are_rejected():
+    import torch
+    say("malformed device regions")
+    vals = torch.from_numpy(workloads.hash_values(1, 4096).view(np.int32)).cuda()
+    bad_offsets = [np.array([0, 100, 50, 4096], np.uint32),          # decreasing
+                   np.array([0, 100, 5000], np.uint32)]               # past n_elements
+    for offs in bad_offsets:
+        for strategy in STRATS:
+            with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:
+                sid = p.push(torch.from_numpy(offs.view(np.int32)).cuda(), vals, n_elements=4096)
+                p.run()
+                with pytest.raises(rs.RsError) as ei:
+                    p.read(sid)
+                assert ei.value.code == rs.RS_EINVAL
+    # text lines that overlap
+    text = torch.from_numpy(np.frombuffer(b"ab cd\nef gh\n" + b" " * 4, np.uint8).copy()).cuda()
+    with rs.Pipeline(rs.RS_TEXT_WORDS, strategy=rs.RS_TAG, ensemble_width=64) as p:
+        sid = p.push(torch.tensor([0, 3], dtype=torch.int32).cuda(), text,
+                     lengths=torch.tensor([5, 5], dtype=torch.int32).cuda(), n_elements=12)
+        p.run()
+        with pytest.raises(rs.RsError):
+            p.read(sid)
+
+
+def test_host_validation_messages():
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=64) as p:
+        with pytest.raises(rs.RsError) as ei:
+            p.push(np.array([0, 5, 3], np.uint32), np.zeros(8, np.uint32))
+        assert ei.value.code == rs.RS_EINVAL and "decrease" in str(ei.value)
+        with pytest.raises(rs.RsError):
+            p.push(np.array([0, 9], np.uint32), np.zeros(8, np.uint32))
+    with rs.Pipeline(rs.RS_GRAPH_THRESH, strategy=rs.RS_TAG, ensemble_width=64) as p:
+        with pytest.raises(rs.RsError):
+            p.push(np.array([0, 2], np.uint32), np.zeros(2, np.uint32))   # thresholds missing
+
+
+# ---- autotuner ----
+
+def test_autotuned_pipeline_matches_oracle(tmp_path, monkeypatch):
+    monkeypatch.setenv("RS_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    say("autotune")
+    for L in (2, 3000):
+        offsets = workloads.fixed_offsets(1 << 19, L)
+        vals = workloads.hash_values(2, 1 << 19)
+        ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+        for _ in range(2):   # second pipeline hits the cache
+            with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_AUTO, ensemble_width=0,
+                             flags=rs.RS_COLLECT_STATS) as p:
+                sid = p.push(offsets, vals)
+                p.run()
+                check(p.read(sid), ref, where=f"autotune L={L}")
+                st = p.stats(sid)
+                assert st.ensemble_width in (64, 128, 256, 512) and st.strategy in (0, 1)
+    lines = (tmp_path / "tune.txt").read_text().split("\n")
+    assert len([l for l in lines if l.strip()]) == 2
+
+
+# ---- serving: continuous batching under an HBM budget ----
+
+def test_serving_results_equal_alone_and_in_the_mix():
+    say("serving")
+    n_req = 48
+    shapes_n, shapes_m = workloads.stream_shapes(seed=5, n_streams=n_req, lo_n=1e3, hi_n=2e5)
+    reqs = [workloads.serving_stream(5, s, int(shapes_n[s]), float(shapes_m[s])) for s in range(n_req)]
+    arrivals = np.sort(workloads.arrivals(6, n_req, 2000.0))
+    refs = [oracle.run(oracle.HASH_EXPAND, o, v) for o, v in reqs]
+    budget = 3 * 1024 * 1024   # total footprint is about 10 MB: admission must gate
+    for per_stream in (False, True):
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256, hbm_budget_bytes=budget) as p:
+            results, timings = p.serve(reqs, arrivals, per_stream=per_stream)
+        for i in range(n_req):
+            assert timings[i]["status"] == 0
+            assert timings[i]["completed"] >= timings[i]["arrival"]
+            check(results[i], refs[i], where=f"serve request {i}")
+        if not per_stream:
+            assert len({t["batch"] for t in timings}) < n_req     # requests shared launches
+    # each request alone gives the same result
+    for i in (0, 7, 31):
+        got, _ = run_one(rs.RS_HASH_EXPAND, rs.RS_SIGNAL, 128, *reqs[i])
+        check(got, refs[i], where=f"alone {i}")
+
+
+def test_serving_rejects_a_request_larger_than_the_budget():
+    o, v = workloads.serving_stream(5, 0, 100000, 10.0)
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256, hbm_budget_bytes=1000) as p:
+        with pytest.raises(rs.RsError) as ei:
+            p.serve([(o, v)], [0.0])
+        assert ei.value.code == rs.RS_EBUDGET
