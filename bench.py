@@ -106,6 +106,80 @@ def probe_copy(rs, torch, stream, nbytes=1 << 30, reps=10):
     return {"copy_bytes": 2 * nbytes, "ms": round(ms, 4), "GB_per_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def serving(rs, torch, stream, n_streams=512, rho=0.8, budget=2 << 30):
+    """512 streams of the serving workload (log-uniform sizes 1e3..1e7, log-uniform mean region
+    length 1..4096, hash/expand pipeline).
+
+    gpu: all streams resident in HBM, one batched persistent launch versus one launch per stream
+         on the same HIP stream (replayed, event-timed).
+    serve: the native request loop on host-memory requests under an HBM budget; capacity is
+         measured with every request arriving at once, then requests arrive as a Poisson process
+         at rho times that capacity; latency is completion minus arrival (host clock).
+    """
+    import workloads
+    n, m = workloads.stream_shapes(seed=5, n_streams=n_streams)
+    reqs = [workloads.serving_stream(5, s, int(n[s]), float(m[s])) for s in range(n_streams)]
+    total = int(n.sum())
+    out = {"streams": n_streams, "elements": total, "hbm_budget_bytes": budget}
+
+    # --- GPU side: batched persistent launch vs one launch per stream
+    dev = [(torch.from_numpy(o.view(np.int32)).cuda(), torch.from_numpy(v.view(np.int32)).cuda()) for o, v in reqs]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_AUTO, ensemble_width=0, flags=rs.RS_COLLECT_STATS) as p:
+        p.set_stream(stream.cuda_stream)
+        ids = [p.push(o, v, n_elements=len(v)) for o, v in dev]
+        p.run()
+        st = p.stats(ids[0])
+        strategy, width = int(st.strategy), int(st.ensemble_width)
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=width) as p:
+        p.set_stream(stream.cuda_stream)
+        for o, v in dev:
+            p.push(o, v, n_elements=len(v))
+        p.run()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(5):
+            p.run_again(rs.RS_RUN_ASYNC)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        batched_ms = e0.elapsed_time(e1) / 5
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=width) as p:
+        p.set_stream(stream.cuda_stream)
+        for rep in range(2):   # the first pass warms up
+            for o, v in dev:
+                p.push(o, v, n_elements=len(v))
+            torch.cuda.synchronize()
+            e0.record(stream)
+            p.run(rs.RS_RUN_PER_STREAM | rs.RS_RUN_ASYNC)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            per_stream_ms = e0.elapsed_time(e1)
+    out["gpu"] = {"strategy": "tag" if strategy == rs.RS_TAG else "signal", "ensemble_width": width,
+                  "batched_ms": round(batched_ms, 3), "batched_elements_per_s": total / (batched_ms * 1e-3),
+                  "per_stream_ms": round(per_stream_ms, 3),
+                  "per_stream_elements_per_s": total / (per_stream_ms * 1e-3)}
+    del dev
+
+    # --- end to end: the request loop on host-memory requests
+    def run_serve(arrivals, per_stream):
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=width, hbm_budget_bytes=budget) as p:
+            _, tim = p.serve(reqs, arrivals, per_stream=per_stream)
+        lat = np.array([t["completed"] - t["arrival"] for t in tim])
+        span = max(t["completed"] for t in tim) - min(t["arrival"] for t in tim)
+        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "elements_per_s": total / span, "launches": len({t["batch"] for t in tim})}
+
+    sat = run_serve(np.zeros(n_streams), False)
+    capacity = sat["elements_per_s"]
+    rate = rho * capacity / (total / n_streams)
+    arrivals = workloads.arrivals(6, n_streams, rate)
+    out["serve"] = {"capacity_elements_per_s": capacity, "rho": rho, "arrival_rate_per_s": rate,
+                    "batched": run_serve(arrivals, False), "per_stream": run_serve(arrivals, True)}
+    return out
+
+
 def cpu_baseline(L, budget_s=12.0):
     """The serial oracle on a bounded sample of the same workload (single thread)."""
     import oracle
@@ -136,6 +210,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", choices=["tag", "signal", "both"], default="both")
     ap.add_argument("--occupancy", action="store_true", help="collect per-node firing statistics in the sweep")
+    ap.add_argument("--no-serving", action="store_true", help="skip the 512-stream batching/serving leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
@@ -209,6 +284,11 @@ def main():
         "hbm_probe": probe,
         "sweep": sweep,
     }
+    if not args.no_serving and not args.headline_only:
+        t_s = time.perf_counter()
+        line["serving"] = serving(rs, torch, stream)
+        print(f"[bench] serving leg {time.perf_counter() - t_s:.1f} s: {json.dumps(line['serving'])}",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(HEADLINE_L)
     print(json.dumps(line))

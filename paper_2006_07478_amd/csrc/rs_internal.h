@@ -63,8 +63,8 @@ struct LaunchArgs {
 // Kernel entry points (defined in rs_kernels.hip).
 // Lanes per workgroup of the kernel for ensemble width w (w = lanes * items per lane).
 uint32_t lanes_of(uint32_t ensemble_width);
-// Most parents one claim may hold: one region-table entry per lane, plus the end offset.
-inline uint32_t claim_parents_max(uint32_t ensemble_width) { return lanes_of(ensemble_width) - 1u; }
+// Most parents one claim may hold (the region table has 256 entries, the last is the end offset).
+inline uint32_t claim_parents_max(uint32_t ensemble_width) { return ensemble_width ? 255u : 0u; }
 bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width);
 int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a,
                     uint32_t grid, void *stream);

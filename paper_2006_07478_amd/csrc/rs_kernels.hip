@@ -128,6 +128,37 @@ __device__ __forceinline__ void ring_w8(uint32_t addr, uint32_t v) {
     asm volatile("ds_write_b8 %0, %1\n\ts_waitcnt lgkmcnt(0)" : : "v"(addr), "v"(v) : "memory");
 }
 
+// N ring bytes at the given LDS addresses, issued together and waited for once, all in
+// one asm statement (no output register may be touched before the wait).
+template <int N>
+__device__ __forceinline__ void ring_read_u8(const uint32_t (&a)[N], uint32_t (&o)[N]) {
+    if constexpr (N == 8) {
+        asm volatile(
+            "ds_read_u8 %0, %8\n\tds_read_u8 %1, %9\n\tds_read_u8 %2, %10\n\tds_read_u8 %3, %11\n\t"
+            "ds_read_u8 %4, %12\n\tds_read_u8 %5, %13\n\tds_read_u8 %6, %14\n\tds_read_u8 %7, %15\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]),
+              "=&v"(o[7])
+            : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7])
+            : "memory");
+    } else if constexpr (N == 4) {
+        asm volatile(
+            "ds_read_u8 %0, %4\n\tds_read_u8 %1, %5\n\tds_read_u8 %2, %6\n\tds_read_u8 %3, %7\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
+            : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3])
+            : "memory");
+    } else if constexpr (N == 2) {
+        asm volatile("ds_read_u8 %0, %2\n\tds_read_u8 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(o[0]), "=&v"(o[1])
+                     : "v"(a[0]), "v"(a[1])
+                     : "memory");
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) o[k] = ring_u8(a[k]);
+    }
+}
+
 // V u32 ring words at the given LDS addresses, issued together, waited for once.
 template <int V>
 __device__ __forceinline__ void ring_read(const uint32_t (&addr)[V], uint32_t (&out)[V]) {
@@ -284,12 +315,13 @@ __device__ __forceinline__ Acc wg_reduce(Acc a, uint32_t *scr) {
 template <int W, int V, bool HAS_E>
 struct Geo {
     static constexpr uint32_t EW = W * V;        // ensemble width: items one firing consumes
-    static constexpr uint32_t BMAX = W - 1;      // parents in one claim, at most (B+1 offsets, one per lane)
+    static constexpr uint32_t R = 256 / W;       // region-table rows per lane
+    static constexpr uint32_t BMAX = R * W - 1;  // parents in one claim, at most (B+1 offsets, R per lane)
     static constexpr uint32_t D1 = 2 * EW;       // data slots in front of the second node
     static constexpr uint32_t D2 = HAS_E ? 4 * EW : 1;   // in front of the third node (k = 3 expansion)
     static constexpr uint32_t SQ = 256;          // signal queue capacity (finite S of §3.1)
     static constexpr uint32_t CHB = 16 * W;      // bytes of one ring chunk: one 16-byte load per lane
-    static constexpr uint32_t NS = 4;            // chunks in the element ring
+    static constexpr uint32_t NS = W == 64 ? 8 : 4;   // chunks in the element ring
     static constexpr uint32_t RING = NS * CHB;
 };
 
@@ -297,11 +329,12 @@ enum Misc : uint32_t {
     M_NEXT = 200, M_JLAST = 201, M_BASE_LO = 202, M_BASE_HI = 203, M_BAD = 204, M_WORDS = 208
 };
 
-// Region table of one claim, as loaded from HBM by one lane (lane t holds parent p0 + t).
+// Region table of one claim, as loaded from HBM: lane t holds parents p0 + r*W + t, r < R.
+template <int R>
 struct ClaimRegs {
-    uint32_t off;      // CSR offsets[p0 + t] (t <= nb), or start of region p0 + t (t < nb)
-    uint32_t len;      // length of region p0 + t (start+length streams)
-    uint32_t ctx;      // per-parent context
+    uint32_t off[R];   // CSR offsets[p0 + i] (i <= nb), or start of region p0 + i (i < nb)
+    uint32_t len[R];   // length of region p0 + i (start+length streams)
+    uint32_t ctx[R];   // per-parent context
 };
 
 // ---------------------------------------------------------------- the pipeline kernel
@@ -337,6 +370,13 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
     const uint32_t t = threadIdx.x;
     const uint32_t wv = t >> 6;
     const uint32_t ring_base = lds_addr(ring);
+    constexpr uint32_t R = G::R;
+    // A single-wave processor needs no hardware barrier: a wave's LDS operations complete in
+    // order, so only the compiler must be kept from moving memory accesses across this point.
+    auto sync = [&]() {
+        if constexpr (W == 64) asm volatile("" ::: "memory");
+        else bar();
+    };
 
     // stage parameters
     const uint32_t modm = a.param[0] ? a.param[0] : 4u;
@@ -358,23 +398,28 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         return lo;
     };
     // this lane's share of the region table of claim gg (loads only; consumed a claim later)
-    auto load_claim = [&](uint32_t gg, ClaimRegs &r) {
-        r.off = r.len = r.ctx = 0;
+    auto load_claim = [&](uint32_t gg, ClaimRegs<R> &r) {
+#pragma unroll
+        for (uint32_t q = 0; q < R; ++q) r.off[q] = r.len[q] = r.ctx[q] = 0;
         if (gg >= a.total_claims) return;
         const StreamDev &sd = a.streams[stream_of(gg)];
         const uint32_t B = sd.parents_per_claim;
         const uint32_t p0 = (gg - sd.claim_begin) * B;
         const uint32_t nb = min(B, sd.n_parents - p0);
-        if constexpr (!BYTES) {
-            if (t <= nb) r.off = sd.offsets[p0 + t];
-        } else {
-            if (t < nb) {
-                r.off = sd.offsets[p0 + t];
-                r.len = sd.lengths[p0 + t];
+#pragma unroll
+        for (uint32_t q = 0; q < R; ++q) {
+            const uint32_t i = q * W + t;
+            if constexpr (!BYTES) {
+                if (i <= nb) r.off[q] = sd.offsets[p0 + i];
+            } else {
+                if (i < nb) {
+                    r.off[q] = sd.offsets[p0 + i];
+                    r.len[q] = sd.lengths[p0 + i];
+                }
             }
-        }
-        if constexpr (CTXP) {
-            if (t < nb) r.ctx = sd.pparam[p0 + t];
+            if constexpr (CTXP) {
+                if (i < nb) r.ctx[q] = sd.pparam[p0 + i];
+            }
         }
     };
 
@@ -386,17 +431,17 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         misc[M_NEXT] = first;
         misc[M_NEXT + 1] = second;
     }
-    bar();
+    sync();
     uint32_t g = uni(misc[M_NEXT]);
     uint32_t g1 = uni(misc[M_NEXT + 1]);
-    ClaimRegs cur;
+    ClaimRegs<R> cur;
     load_claim(g, cur);
-    bar();
+    sync();
 
     while (g < a.total_claims) {
         uint32_t g_next = 0;
         if (t == 0) g_next = atomicAdd(&a.ctl[CTL_CLAIM], 1u);   // the claim after g1
-        ClaimRegs nxt;
+        ClaimRegs<R> nxt;
         load_claim(g1, nxt);                                      // consumed at the next claim
 
         const StreamDev &sd = a.streams[stream_of(g)];
@@ -410,46 +455,57 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         // ---- region table of the claim (enumeration: findCount per parent)
         uint32_t vbeg, vend;
         if constexpr (!BYTES) {
-            if (t <= nb) VT[t] = cur.off;
-            if constexpr (CTXP)
-                if (t < nb) CX[t] = cur.ctx;
-            bar();
+#pragma unroll
+            for (uint32_t q = 0; q < R; ++q) {
+                const uint32_t i = q * W + t;
+                if (i <= nb) VT[i] = cur.off[q];
+                if constexpr (CTXP)
+                    if (i < nb) CX[i] = cur.ctx[q];
+            }
+            sync();
             vbeg = uni(VT[0]);
             vend = uni(VT[nb]);
         } else {
-            if (t < nb) SX[t] = cur.off;
-            uint32_t tot;
-            const uint32_t ex = wg_scan_u32<W>(t < nb ? cur.len : 0u, misc, tot);
-            if (t < nb) VT[t] = ex;
-            if (t == 0) VT[nb] = tot;
-            bar();
+            uint32_t carry = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < R; ++q) {
+                const uint32_t i = q * W + t;
+                if (i < nb) SX[i] = cur.off[q];
+                uint32_t tot;
+                const uint32_t ex = wg_scan_u32<W>(i < nb ? cur.len[q] : 0u, misc, tot);
+                if (i < nb) VT[i] = carry + ex;
+                carry += tot;
+                sync();
+            }
+            if (t == 0) VT[nb] = carry;
+            sync();
             vbeg = 0;
-            vend = tot;
+            vend = carry;
         }
-        if (t < nb) {
-            s_cnt[t] = 0;
-            s_sum[t] = 0ull;
-            s_min[t] = 0xFFFFFFFFu;
-            s_max[t] = 0;
+        for (uint32_t i = t; i < nb; i += W) {
+            s_cnt[i] = 0;
+            s_sum[i] = 0ull;
+            s_min[i] = 0xFFFFFFFFu;
+            s_max[i] = 0;
         }
 
         // The claim's regions must be ordered and inside the element array before any element
         // is read; a malformed stream is flagged and its claims are skipped.
         {
             bool bad = false;
-            if (t < nb) {
+            for (uint32_t i = t; i < nb; i += W) {
                 if constexpr (!BYTES) {
-                    bad = (VT[t] > VT[t + 1]) || (t + 1u == nb && VT[nb] > sd.n_elements);
+                    bad |= (VT[i] > VT[i + 1]) || (i + 1u == nb && VT[nb] > sd.n_elements);
                 } else {
-                    const unsigned long long end = (unsigned long long)SX[t] + (VT[t + 1] - VT[t]);
-                    const unsigned long long lim = (t + 1u < nb) ? SX[t + 1] : sd.n_elements;
-                    bad = end > lim;
+                    const unsigned long long end = (unsigned long long)SX[i] + (VT[i + 1] - VT[i]);
+                    const unsigned long long lim = (i + 1u < nb) ? SX[i + 1] : sd.n_elements;
+                    bad |= end > lim;
                 }
             }
             if (t == 0) misc[M_BAD] = 0;
-            bar();
+            sync();
             if (bad) misc[M_BAD] = 1;
-            bar();
+            sync();
             if (uni(misc[M_BAD])) {
                 if (t == 0) {
                     atomicOr((unsigned int *)&sd.stats[ST_ERROR], 1u);
@@ -458,7 +514,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     misc[M_NEXT] = g_next;
                 }
-                bar();
+                sync();
                 g = g1;
                 g1 = uni(misc[M_NEXT]);
                 cur = nxt;
@@ -504,7 +560,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                     const uint32_t dst = ring_base + (ld_ready % G::NS) * G::CHB + t * 16u;
                     for (uint32_t k2 = 0; blk + k2 < nbytes_total; ++k2) ring_w8(dst + k2, elems[blk + k2]);
                 }
-                bar();
+                sync();
                 ++ld_ready;
             }
         };
@@ -517,7 +573,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         auto ring_drain = [&]() {
             if (ld_ready < ld_next) {   // chunks issued beyond what was read (look-ahead margin)
                 wait_vm<0>();
-                bar();
+                sync();
             }
             ld_next = 0;
             ld_ready = 0;
@@ -598,6 +654,8 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                     }
                 }
             } else {
+                uint32_t ab[2 * V], bv[2 * V];
+                bool in_line[V], at_start[V];
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
                     const uint32_t i = (uint32_t)k * W + t;
@@ -607,12 +665,16 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                     const uint32_t ls = SX[j];
                     const uint32_t adr = TAG ? v : ls + (v - VT[j]);
                     item[k] = adr;
-                    const bool in_line = i < e && (!TAG || adr < ls + (VT[j + 1] - VT[j]));
-                    if (in_line) {
-                        const uint32_t b = ring_u8(ring_off(adr));
-                        const uint32_t prev = (adr == ls) ? 32u : ring_u8(ring_off(adr - 1u));
-                        keep[k] = (b != 32u) && (prev == 32u);
-                    }
+                    in_line[k] = i < e && (!TAG || adr < ls + (VT[j + 1] - VT[j]));
+                    at_start[k] = adr == ls;
+                    ab[2 * k] = in_line[k] ? ring_off(adr) : ring_base;
+                    ab[2 * k + 1] = (in_line[k] && !at_start[k]) ? ring_off(adr - 1u) : ring_base;
+                }
+                ring_read_u8<2 * V>(ab, bv);
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const uint32_t prev = at_start[k] ? 32u : bv[2 * k + 1];
+                    keep[k] = in_line[k] && (bv[2 * k] != 32u) && (prev == 32u);
                 }
             }
         };
@@ -644,7 +706,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                         if ((uint32_t)k * W + t == e - 1u) misc[M_JLAST] = reg[k];
                 }
                 fpos += e;
-                bar();
+                sync();
                 if constexpr (TAG) {
                     jlo = uni(misc[M_JLAST]);
                     fdone = (fpos == vend);
@@ -680,7 +742,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                 misc[M_BASE_LO] = (uint32_t)prefix;
                 misc[M_BASE_HI] = (uint32_t)(prefix >> 32);
             }
-            bar();
+            sync();
             out_base_lo = uni(misc[M_BASE_LO]);
             out_base_hi = uni(misc[M_BASE_HI]);
         }
@@ -797,7 +859,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                             st_sig[2] += 1;
                         }
                     }
-                    bar();
+                    sync();
                     continue;
                 }
             }
@@ -834,17 +896,31 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                                 if constexpr (KIND == RS_HASH_EXPAND) {
                                     nout[k] = q1a[pos];
                                 } else {
-                                    // word length: run of non-space bytes from the start, within the line
+                                    // word length: run of non-space bytes from the start, within the line,
+                                    // read four bytes at a time from the ring (global memory outside it)
                                     const uint32_t j = TAG ? tg[k] : ej;
                                     const uint32_t le = SX[j] + (VT[j + 1] - VT[j]);
                                     const uint32_t wlo = A0 + (ld_next > G::NS ? ld_next - G::NS : 0u) * G::CHB;
                                     const uint32_t whi = A0 + ld_ready * G::CHB;
                                     uint32_t p = x[k];
                                     while (p < le) {
-                                        const uint32_t b =
-                                            (p >= wlo && p < whi) ? ring_u8(ring_off(p)) : (uint32_t)elems[p];
-                                        if (b == 32u) break;
-                                        ++p;
+                                        const uint32_t q = p & ~3u;
+                                        uint32_t word = 0;
+                                        if (q >= wlo && q + 8u <= whi) {
+                                            uint32_t w0, w1;
+                                            ring_u32x2(ring_off(q), ring_off(q + 4u), w0, w1);
+                                            word = __builtin_amdgcn_alignbyte(w1, w0, p & 3u);
+                                        } else {
+                                            for (uint32_t b = 0; b < 4u && p + b < le; ++b)
+                                                word |= (uint32_t)elems[p + b] << (8u * b);
+                                        }
+                                        // first space among the four bytes: zero byte of word ^ "    "
+                                        const uint32_t z = word ^ 0x20202020u;
+                                        const uint32_t zm = (z - 0x01010101u) & ~z & 0x80808080u;
+                                        uint32_t step = zm ? ((uint32_t)__builtin_ctz(zm) >> 3) : 4u;
+                                        if (le - p < step) step = le - p;
+                                        p += step;
+                                        if (step < 4u) break;
                                     }
                                     x[k] = p - x[k];
                                     nout[k] = 1;
@@ -894,7 +970,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                             st_sig[1] += 1;
                         }
                     }
-                    bar();
+                    sync();
                     continue;
                 }
             }
@@ -952,7 +1028,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                             fdone = (fj == nb);
                         }
                     }
-                    bar();
+                    sync();
                     if constexpr (TAG) {
                         if (e) jlo = uni(misc[M_JLAST]);
                         fdone = (fpos == vend);
@@ -968,18 +1044,18 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
 
         if constexpr (TAG) {
             flush_tag();
-            bar();
+            sync();
         }
         ring_drain();
         if (failed && t == 0) atomicOr(&a.ctl[CTL_ERROR], 1u);
 
         // ---- end(): one record per parent, written once
-        if (t < nb) {
-            const uint32_t p = p0 + t;
-            if (a.agg_fields & RS_COUNT) sd.agg_count[p] = s_cnt[t];
-            if (a.agg_fields & RS_SUM) sd.agg_sum[p] = s_sum[t];
-            if (a.agg_fields & RS_MIN) sd.agg_min[p] = s_min[t];
-            if (a.agg_fields & RS_MAX) sd.agg_max[p] = s_max[t];
+        for (uint32_t i = t; i < nb; i += W) {
+            const uint32_t p = p0 + i;
+            if (a.agg_fields & RS_COUNT) sd.agg_count[p] = s_cnt[i];
+            if (a.agg_fields & RS_SUM) sd.agg_sum[p] = s_sum[i];
+            if (a.agg_fields & RS_MIN) sd.agg_min[p] = s_min[i];
+            if (a.agg_fields & RS_MAX) sd.agg_max[p] = s_max[i];
         }
         if (a.collect_stats && t == 0) {
             for (int k = 0; k < 3; ++k) {
@@ -990,7 +1066,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
             }
         }
         if (t == 0) misc[M_NEXT] = g_next;
-        bar();
+        sync();
         g = g1;
         g1 = uni(misc[M_NEXT]);
         cur = nxt;
@@ -1012,15 +1088,16 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
 
 using KernelFn = void (*)(LaunchArgs);
 
-// Ensemble width w = W * V: W lanes per workgroup, V items per lane per firing.
+// Ensemble width w = W * V: W lanes per workgroup, V items per lane per firing.  Every width
+// runs on single-wave processors: a wave's lanes share one scheduler with no barrier.
 template <int KIND, int STRAT>
 static KernelFn pick_width(uint32_t w) {
     switch (w) {
         case 64: return rs_pipeline<KIND, STRAT, 64, 1>;
-        case 128: return rs_pipeline<KIND, STRAT, 128, 1>;
-        case 256: return rs_pipeline<KIND, STRAT, 256, 1>;
-        case 512: return rs_pipeline<KIND, STRAT, 256, 2>;
-        case 1024: return rs_pipeline<KIND, STRAT, 256, 4>;
+        case 128: return rs_pipeline<KIND, STRAT, 64, 2>;
+        case 256: return rs_pipeline<KIND, STRAT, 64, 4>;
+        case 512: return rs_pipeline<KIND, STRAT, 64, 8>;
+        case 1024: return rs_pipeline<KIND, STRAT, 64, 16>;
         default: return nullptr;
     }
 }
@@ -1040,7 +1117,7 @@ static KernelFn pick(uint32_t kind, uint32_t s, uint32_t w) {
     }
 }
 
-uint32_t lanes_of(uint32_t ensemble_width) { return ensemble_width > 256 ? 256u : ensemble_width; }
+uint32_t lanes_of(uint32_t ensemble_width) { return ensemble_width ? 64u : 0u; }
 
 // ---------------------------------------------------------------- HBM probe
 

@@ -246,8 +246,10 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     for (size_t i = 0; i < sel.size(); ++i) {
         Stream *s = sel[i];
         uint32_t P = s->n_parents;
-        if (probe && s->n_elements > (1u << 22) && P > 1)   // probe on a prefix of about 2^22 elements
-            P = (uint32_t)std::max<uint64_t>(1, (uint64_t)((double)P * (double)(1u << 22) / s->n_elements));
+        // probe on a prefix of about 2^25 elements: enough claims to fill every compute unit,
+        // so the timing ranks configurations as the full stream would
+        if (probe && s->n_elements > (1u << 25) && P > 1)
+            P = (uint32_t)std::max<uint64_t>(1, (uint64_t)((double)P * (double)(1u << 25) / s->n_elements));
         plan_claims(s, p->width, P);
         rs::StreamDev &e = h[i];
         std::memset(&e, 0, sizeof e);
@@ -835,8 +837,9 @@ RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view
     };
     while (done < n) {
         bool progressed = false;
-        // 1. arrivals: push every request whose time has come
-        while (next < n && reqs[next].arrival_s <= now()) {
+        // 1. arrivals: push requests whose time has come, a few per pass so that launches and
+        //    completions are not held up behind a long run of copies
+        for (int pushed = 0; pushed < 4 && next < n && reqs[next].arrival_s <= now(); ++pushed) {
             uint64_t id = 0;
             const int rc = stream_push(p, &reqs[next].stream, &id);
             if (rc) {
