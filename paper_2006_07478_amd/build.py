@@ -9,7 +9,7 @@ OUT = os.path.join(HERE, "libregionstream.so")
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
                "-Wall", "-Wno-unused-parameter",
-               # packed fp32 instructions stay off (this pool has seen them misbehave)
+               # packed fp32 instructions stay off: some of their forms have given wrong results with no error
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-I" + os.path.join(ROOT, "include")]
 

@@ -50,14 +50,14 @@ struct StreamDev {
 struct LaunchArgs {
     const StreamDev *streams;
     uint32_t *ctl;
-    const void *dummy;             // 16 readable bytes: source of ring lanes past a stream's end
     uint32_t n_streams;
     uint32_t total_claims;
     uint32_t param[4];
     uint32_t agg_fields;
     uint32_t collect_stats;
     uint32_t emit_outputs;
-    uint32_t pad;
+    uint32_t bmax;                 // most parents in any claim of the launch (sizes the per-claim LDS)
+    uint32_t pad[3];
 };
 
 // Kernel entry points (defined in rs_kernels.hip).
@@ -68,7 +68,9 @@ inline uint32_t claim_parents_max(uint32_t ensemble_width) { return ensemble_wid
 bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width);
 int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a,
                     uint32_t grid, void *stream);
-int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width);
+int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t bmax);
+// Bytes of per-claim LDS (region table and aggregate slots) for claims of up to bmax parents.
+uint32_t dyn_lds_bytes(uint32_t kind, uint32_t bmax);
 int launch_probe_copy(const void *src, void *dst, unsigned long long bytes, uint32_t n_cu, void *stream);
 
 

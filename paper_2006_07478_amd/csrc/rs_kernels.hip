@@ -1,35 +1,34 @@
 // gfx950 kernels of the region-stateful streaming pipeline.
 //
-// One workgroup of W lanes is one SIMD processor in the sense of §2.2: it runs a
-// whole pipeline instance (enumerating node F, optional second node E, aggregating
-// node A) with a non-preemptive scheduler, and it competes with every other
-// workgroup for parent batches ("claims") through a device atomic on a common
-// counter, returning only when every claim of every stream in the launch is done.
-// A firing of a node consumes an ensemble of at most w = W*V items: item i of the
-// ensemble sits on lane i mod W, in round i / W, so one firing is V rounds of
-// W-wide SIMD work.
+// One wave64 workgroup is one SIMD processor in the sense of §2.2: it runs a whole
+// pipeline instance (enumerating node F, optional second node E, aggregating node A)
+// under a non-preemptive scheduler whose state is wave-uniform and lives in scalar
+// registers, and it competes with every other wave for parent batches ("claims")
+// through a device atomic, returning only when every claim of the launch is done.
+// A firing consumes an ensemble of at most w = 64*V items: item i sits on lane
+// i mod 64 in round i / 64, so one firing is V rounds of 64-lane SIMD work.
 //
-// Nodes are joined by fixed-size LDS queues.  Data-dependent output counts are
-// compacted with wave64 ballot/mbcnt ranks plus an LDS prefix over the waves.
+// Nodes are joined by LDS data queues.  Data-dependent output counts are compacted
+// with ballot/mbcnt ranks; every lane writes every round, items that a firing drops
+// going to a per-lane spill slot past the queue, so no queue write is predicated.
 // Region boundaries travel either
-//   - as signals (RS_SIGNAL): an end-of-region slot sits in the data queue at its
-//     exact stream position and a small signal queue records where the slots are;
-//     the items between two slots are that signal's credit (the in-band form of the
-//     credit protocol of §3.1), a consumer's ensemble never extends past the next
-//     slot (the SIMD rule of §3.3), and a node consumes a slot only when no item
-//     precedes it, running end() for that region; or
+//   - as signals (RS_SIGNAL): each edge has a signal queue S next to its data queue Q
+//     (§3.1); an entry is the Q position the signal follows, so the items between two
+//     signals are that signal's credit.  A consumer's ensemble never extends past the
+//     next signal (the SIMD rule of §3.3) and a node handles a signal only when no item
+//     precedes it, running end() for that region.  S is one VGPR, entry n in lane
+//     n mod 64, read with readlane and written with a lane select (no LDS round trip); or
 //   - as tags (RS_TAG): every queued item carries its region index, ensembles mix
 //     regions freely, and the aggregating node reduces by tag (§5).
-// Aggregates are exact integer reductions kept in LDS slots per claim and written
-// once per parent; a claim always holds whole regions, so no aggregate is ever
-// shared between workgroups.
+// Aggregates are exact integer reductions kept in LDS slots per claim and written once
+// per parent; a claim always holds whole regions, so no aggregate is ever shared
+// between waves.
 //
-// Elements reach the enumerating node through an LDS ring filled by direct
-// global->LDS loads (global_load_lds_dwordx4), NS chunks deep, independent of
-// where ensembles or regions begin; the next claim's region table is loaded into
-// registers while the current claim runs.  The compiler does not track which chunk
-// a read touches, so the ring is read with inline-asm ds_read and completion is
-// managed with explicit vmcnt waits and a barrier that does not drain vmcnt.
+// Elements reach the enumerating node from HBM through direct buffer->LDS loads into a
+// one-ensemble staging slot; the next firing's ensemble is requested as soon as the
+// current one is taken, so the loads overlap the downstream firings, and their
+// completion is awaited explicitly.  The next claim's region table is loaded into
+// registers while the current claim runs.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -53,7 +52,7 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
 // Salt s of the stage hash: H(x, s) = fmix32(x ^ (0x9E3779B9 * (s + 1))).
 __device__ __forceinline__ constexpr uint32_t salt_key(uint32_t s) { return 0x9E3779B9u * (s + 1u); }
 
-// ---------------------------------------------------------------- wave / workgroup helpers
+// ---------------------------------------------------------------- wave helpers
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -61,196 +60,52 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Workgroup barrier that waits for this wave's LDS operations only (not for
-// outstanding global->LDS chunk loads, whose completion is waited for explicitly).
-__device__ __forceinline__ void bar() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-// Wait until at most N vector-memory operations of this wave are outstanding.
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-__device__ __forceinline__ void wait_vm_n(uint32_t n) {
-    switch (n) {
-        case 0: wait_vm<0>(); break;
-        case 1: wait_vm<1>(); break;
-        case 2: wait_vm<2>(); break;
-        case 3: wait_vm<3>(); break;
-        case 4: wait_vm<4>(); break;
-        case 5: wait_vm<5>(); break;
-        case 6: wait_vm<6>(); break;
-        default: wait_vm<7>(); break;
-    }
-}
+// Lanes of one wave see each other's LDS writes in issue order; this only keeps the
+// compiler from moving memory accesses across the point.
+__device__ __forceinline__ void order() { asm volatile("" ::: "memory"); }
 
 typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) void glb_void_t;
 
-__device__ __forceinline__ uint32_t lds_addr(const void *p) {
-    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
-}
-
-// Reads of the element ring, hidden from the compiler's wait insertion.
-__device__ __forceinline__ uint32_t ring_u32(uint32_t addr) {
-    uint32_t v;
-    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr) : "memory");
-    return v;
-}
-__device__ __forceinline__ void ring_u32x4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t &v0,
-                                           uint32_t &v1, uint32_t &v2, uint32_t &v3) {
-    asm volatile(
-        "ds_read_b32 %0, %4\n\t"
-        "ds_read_b32 %1, %5\n\t"
-        "ds_read_b32 %2, %6\n\t"
-        "ds_read_b32 %3, %7\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
-        : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
-        : "memory");
-}
-__device__ __forceinline__ void ring_u32x2(uint32_t a0, uint32_t a1, uint32_t &v0, uint32_t &v1) {
-    asm volatile(
-        "ds_read_b32 %0, %2\n\t"
-        "ds_read_b32 %1, %3\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(v0), "=&v"(v1)
-        : "v"(a0), "v"(a1)
-        : "memory");
-}
-__device__ __forceinline__ uint32_t ring_u8(uint32_t addr) {
-    uint32_t v;
-    asm volatile("ds_read_u8 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr) : "memory");
-    return v;
-}
-__device__ __forceinline__ void ring_w8(uint32_t addr, uint32_t v) {
-    asm volatile("ds_write_b8 %0, %1\n\ts_waitcnt lgkmcnt(0)" : : "v"(addr), "v"(v) : "memory");
+// Buffer resource over [base, base + bytes): loads outside the range return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// N ring bytes at the given LDS addresses, issued together and waited for once, all in
-// one asm statement (no output register may be touched before the wait).
-template <int N>
-__device__ __forceinline__ void ring_read_u8(const uint32_t (&a)[N], uint32_t (&o)[N]) {
-    if constexpr (N == 8) {
-        asm volatile(
-            "ds_read_u8 %0, %8\n\tds_read_u8 %1, %9\n\tds_read_u8 %2, %10\n\tds_read_u8 %3, %11\n\t"
-            "ds_read_u8 %4, %12\n\tds_read_u8 %5, %13\n\tds_read_u8 %6, %14\n\tds_read_u8 %7, %15\n\t"
-            "s_waitcnt lgkmcnt(0)"
-            : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]),
-              "=&v"(o[7])
-            : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7])
-            : "memory");
-    } else if constexpr (N == 4) {
-        asm volatile(
-            "ds_read_u8 %0, %4\n\tds_read_u8 %1, %5\n\tds_read_u8 %2, %6\n\tds_read_u8 %3, %7\n\t"
-            "s_waitcnt lgkmcnt(0)"
-            : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
-            : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3])
-            : "memory");
-    } else if constexpr (N == 2) {
-        asm volatile("ds_read_u8 %0, %2\n\tds_read_u8 %1, %3\n\ts_waitcnt lgkmcnt(0)"
-                     : "=&v"(o[0]), "=&v"(o[1])
-                     : "v"(a[0]), "v"(a[1])
-                     : "memory");
-    } else {
-#pragma unroll
-        for (int k = 0; k < N; ++k) o[k] = ring_u8(a[k]);
+// Rounds K.. of a staged ensemble copy: round k moves words k*64 + lane from the buffer to
+// LDS; the instruction's immediate offset advances both the buffer and the LDS address.
+template <int K, int V>
+__device__ __forceinline__ void stage_rounds(__amdgpu_buffer_rsrc_t r, lds_void_t *dst, uint32_t voff) {
+    if constexpr (K < V) {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, voff, 0, K * 256, 0);
+        stage_rounds<K + 1, V>(r, dst, voff);
     }
 }
 
-// V u32 ring words at the given LDS addresses, issued together, waited for once.
-template <int V>
-__device__ __forceinline__ void ring_read(const uint32_t (&addr)[V], uint32_t (&out)[V]) {
-    if constexpr (V == 4) {
-        ring_u32x4(addr[0], addr[1], addr[2], addr[3], out[0], out[1], out[2], out[3]);
-    } else if constexpr (V == 2) {
-        ring_u32x2(addr[0], addr[1], out[0], out[1]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < V; ++k) out[k] = ring_u32(addr[k]);
-    }
-}
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
 
 // Exclusive prefix of per-item counts n[k] (0..3) over an ensemble laid out as item
-// k*W + lane, in that order.  off[k] is the item's first output slot relative to the
-// firing's base; total is the firing's output count (uniform).
-template <int W, int V, bool TWO_BITS>
-__device__ __forceinline__ void ens_scan(const uint32_t (&n)[V], uint32_t (&off)[V], uint32_t &total,
-                                         uint32_t *scr) {
-    constexpr uint32_t NW = W / 64;
-    uint32_t within[V], wsum[V];
+// k*64 + lane, in that order.  off[k] is the item's first output slot relative to the
+// firing's base; the return value is the firing's output count (uniform).
+template <int V, bool TWO_BITS>
+__device__ __forceinline__ uint32_t ens_scan(const uint32_t (&n)[V], uint32_t (&off)[V]) {
+    uint32_t run = 0;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         const uint64_t b0 = __ballot(n[k] & 1u);
-        within[k] = rank_below(b0);
-        wsum[k] = (uint32_t)__popcll(b0);
+        uint32_t within = rank_below(b0);
+        uint32_t wsum = (uint32_t)__popcll(b0);
         if constexpr (TWO_BITS) {
             const uint64_t b1 = __ballot((n[k] >> 1) & 1u);
-            within[k] += 2u * rank_below(b1);
-            wsum[k] += 2u * (uint32_t)__popcll(b1);
+            within += 2u * rank_below(b1);
+            wsum += 2u * (uint32_t)__popcll(b1);
         }
+        off[k] = run + within;
+        run += wsum;
     }
-    if constexpr (NW == 1) {
-        uint32_t run = 0;
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            off[k] = run + within[k];
-            run += wsum[k];
-        }
-        total = uni(run);
-    } else {
-        const uint32_t wv = threadIdx.x >> 6;
-        if ((threadIdx.x & 63u) == 0) {
-#pragma unroll
-            for (int k = 0; k < V; ++k) scr[k * NW + wv] = wsum[k];
-        }
-        bar();
-        uint32_t run = 0;
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            uint32_t before = 0, all = 0;
-#pragma unroll
-            for (uint32_t w = 0; w < NW; ++w) {
-                const uint32_t s = scr[k * NW + w];
-                before += (w < wv) ? s : 0u;
-                all += s;
-            }
-            off[k] = run + before + within[k];
-            run += all;
-        }
-        total = uni(run);
-    }
-}
-
-// Exclusive prefix of arbitrary u32 values over the workgroup (one per lane).
-template <int W>
-__device__ __forceinline__ uint32_t wg_scan_u32(uint32_t v, uint32_t *scr, uint32_t &total) {
-    const uint32_t ln = threadIdx.x & 63u;
-    uint32_t inc = v;
-#pragma unroll
-    for (uint32_t o = 1; o < 64; o <<= 1) {
-        const uint32_t u = __shfl_up(inc, o, 64);
-        if (ln >= o) inc += u;
-    }
-    const uint32_t wsum = __shfl(inc, 63, 64);
-    if constexpr (W == 64) {
-        total = uni(wsum);
-        return inc - v;
-    } else {
-        const uint32_t wv = threadIdx.x >> 6;
-        if (ln == 63u) scr[wv] = wsum;
-        bar();
-        uint32_t before = 0, all = 0;
-#pragma unroll
-        for (uint32_t i = 0; i < (uint32_t)W / 64u; ++i) {
-            const uint32_t s = scr[i];
-            before += (i < wv) ? s : 0u;
-            all += s;
-        }
-        total = uni(all);
-        return before + inc - v;
-    }
+    return uni(run);
 }
 
 struct Acc {
@@ -265,16 +120,17 @@ __device__ __forceinline__ void acc_reset(Acc &a) {
     a.mn = 0xFFFFFFFFu;
     a.mx = 0;
 }
-__device__ __forceinline__ void acc_add(Acc &a, uint32_t y) {
-    a.cnt += 1u;
-    a.sum += (unsigned long long)y;
-    a.mn = a.mn < y ? a.mn : y;
-    a.mx = a.mx > y ? a.mx : y;
+// Adds y when act holds, without a branch.
+__device__ __forceinline__ void acc_add(Acc &a, uint32_t y, bool act) {
+    a.cnt += act ? 1u : 0u;
+    a.sum += (unsigned long long)(act ? y : 0u);
+    const uint32_t lo = act ? y : 0xFFFFFFFFu, hi = act ? y : 0u;
+    a.mn = a.mn < lo ? a.mn : lo;
+    a.mx = a.mx > hi ? a.mx : hi;
 }
 
-// Workgroup reduction of per-lane accumulators; every lane gets the result.
-template <int W>
-__device__ __forceinline__ Acc wg_reduce(Acc a, uint32_t *scr) {
+// Wave reduction of per-lane accumulators; every lane gets the result.
+__device__ __forceinline__ Acc wave_reduce(Acc a) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         a.cnt += __shfl_xor(a.cnt, o, 64);
@@ -284,52 +140,48 @@ __device__ __forceinline__ Acc wg_reduce(Acc a, uint32_t *scr) {
         a.mn = a.mn < m0 ? a.mn : m0;
         a.mx = a.mx > m1 ? a.mx : m1;
     }
-    if constexpr (W == 64) {
-        return a;
-    } else {
-        constexpr uint32_t NW = W / 64;
-        const uint32_t wv = threadIdx.x >> 6;
-        if ((threadIdx.x & 63u) == 0) {
-            scr[64 + wv] = a.cnt;
-            scr[80 + 2 * wv] = (uint32_t)a.sum;
-            scr[81 + 2 * wv] = (uint32_t)(a.sum >> 32);
-            scr[112 + wv] = a.mn;
-            scr[128 + wv] = a.mx;
-        }
-        bar();
-        Acc r;
-        acc_reset(r);
-#pragma unroll
-        for (uint32_t i = 0; i < NW; ++i) {
-            r.cnt += scr[64 + i];
-            r.sum += (unsigned long long)scr[80 + 2 * i] | ((unsigned long long)scr[81 + 2 * i] << 32);
-            r.mn = r.mn < scr[112 + i] ? r.mn : scr[112 + i];
-            r.mx = r.mx > scr[128 + i] ? r.mx : scr[128 + i];
-        }
-        return r;
-    }
+    return a;
 }
 
 // ---------------------------------------------------------------- geometry
 
-template <int W, int V, bool HAS_E>
+template <int V, bool HAS_E, uint32_t KE>
 struct Geo {
-    static constexpr uint32_t EW = W * V;        // ensemble width: items one firing consumes
-    static constexpr uint32_t R = 256 / W;       // region-table rows per lane
-    static constexpr uint32_t BMAX = R * W - 1;  // parents in one claim, at most (B+1 offsets, R per lane)
-    static constexpr uint32_t D1 = 2 * EW;       // data slots in front of the second node
-    static constexpr uint32_t D2 = HAS_E ? 4 * EW : 1;   // in front of the third node (k = 3 expansion)
-    static constexpr uint32_t SQ = 256;          // signal queue capacity (finite S of §3.1)
-    static constexpr uint32_t CHB = 16 * W;      // bytes of one ring chunk: one 16-byte load per lane
-    static constexpr uint32_t NS = W == 64 ? 8 : 4;   // chunks in the element ring
-    static constexpr uint32_t RING = NS * CHB;
+    static constexpr uint32_t EW = 64u * V;   // ensemble width: items one firing consumes
+    static constexpr uint32_t D1 = 2u * EW;   // data slots in front of the second node
+    // in front of the third node: room for one full ensemble's worst-case output on top
+    // of an almost full ensemble, so the second node always fires full ensembles
+    static constexpr uint32_t D2 = HAS_E ? (KE == 3u ? 4u * EW : 2u * EW) : 1u;
+    static constexpr uint32_t SQ = 64u;       // signal queue capacity (the finite S of §3.1)
+    static constexpr uint32_t R = 4u;         // region-table rows per lane (256 entries)
 };
 
-enum Misc : uint32_t {
-    M_NEXT = 200, M_JLAST = 201, M_BASE_LO = 202, M_BASE_HI = 203, M_BAD = 204, M_WORDS = 208
+// Per-claim LDS arrays, sized at launch for the batch's largest claim (bmax parents).
+struct Dyn {
+    uint32_t sum, vt, sx, cx, cnt, mn, mx, bytes;
 };
+__host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t bmax) {
+    Dyn d;
+    uint32_t o = 0;
+    d.sum = o;
+    o += 8u * bmax;   // u64 slots first (8-byte aligned)
+    d.vt = o;
+    o += 4u * (bmax + 1u);
+    d.sx = o;
+    if (kind == RS_TEXT_WORDS) o += 4u * bmax;
+    d.cx = o;
+    if (kind == RS_GRAPH_THRESH) o += 4u * bmax;
+    d.cnt = o;
+    o += 4u * bmax;
+    d.mn = o;
+    o += 4u * bmax;
+    d.mx = o;
+    o += 4u * bmax;
+    d.bytes = (o + 15u) & ~15u;
+    return d;
+}
 
-// Region table of one claim, as loaded from HBM: lane t holds parents p0 + r*W + t, r < R.
+// Region table of one claim, as loaded from HBM: lane t holds parents p0 + r*64 + t.
 template <int R>
 struct ClaimRegs {
     uint32_t off[R];   // CSR offsets[p0 + i] (i <= nb), or start of region p0 + i (i < nb)
@@ -339,44 +191,36 @@ struct ClaimRegs {
 
 // ---------------------------------------------------------------- the pipeline kernel
 
-template <int KIND, int STRAT, int W, int V>
-__global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
+template <int KIND, int STRAT, int V>
+__global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     constexpr bool TAG = (STRAT == RS_TAG);
     constexpr bool HAS_E = (KIND == RS_HASH_EXPAND || KIND == RS_TEXT_WORDS);
     constexpr bool BYTES = (KIND == RS_TEXT_WORDS);
     constexpr bool CTXP = (KIND == RS_GRAPH_THRESH);
-    constexpr uint32_t EB = BYTES ? 1u : 4u;                       // element bytes
-    constexpr uint32_t KE = (KIND == RS_HASH_EXPAND) ? 3u : 1u;    // outputs per input of E
-    using G = Geo<W, V, HAS_E>;
-    constexpr uint32_t EW = G::EW;
+    constexpr uint32_t KE = (KIND == RS_HASH_EXPAND) ? 3u : 1u;   // outputs per input of E, at most
+    using G = Geo<V, HAS_E, KE>;
+    constexpr uint32_t EW = G::EW, D1 = G::D1, D2 = G::D2, SQ = G::SQ, R = G::R;
+    constexpr uint32_t DA = HAS_E ? D2 : D1;   // the aggregating node's input queue
 
-    __shared__ __attribute__((aligned(16))) uint8_t ring[G::RING];
-    __shared__ uint32_t VT[G::BMAX + 1];             // region starts in enumeration order, end at [nb]
-    __shared__ uint32_t SX[BYTES ? G::BMAX : 1];     // region start addresses (start+length streams)
-    __shared__ uint32_t CX[CTXP ? G::BMAX : 1];      // per-parent context
-    __shared__ uint32_t s_cnt[G::BMAX];
-    __shared__ unsigned long long s_sum[G::BMAX];
-    __shared__ uint32_t s_min[G::BMAX];
-    __shared__ uint32_t s_max[G::BMAX];
-    __shared__ uint32_t q1v[G::D1];
-    __shared__ uint8_t q1a[KIND == RS_HASH_EXPAND ? G::D1 : 1];
-    __shared__ uint16_t q1t[TAG ? G::D1 : 1];
-    __shared__ uint32_t sp1[TAG ? 1 : G::SQ];
-    __shared__ uint32_t q2v[G::D2];
-    __shared__ uint16_t q2t[(HAS_E && TAG) ? G::D2 : 1];
-    __shared__ uint32_t sp2[(HAS_E && !TAG) ? G::SQ : 1];
-    __shared__ uint32_t misc[M_WORDS];
+    // data queues, each followed by 64 spill slots (one per lane) for dropped items
+    __shared__ uint32_t q1v[D1 + 64];
+    __shared__ uint8_t q1a[KIND == RS_HASH_EXPAND ? D1 + 64 : 1];
+    __shared__ uint8_t q1t[TAG ? D1 + 64 : 1];
+    __shared__ uint32_t q2v[HAS_E ? D2 + 64 : 1];
+    __shared__ uint8_t q2t[(HAS_E && TAG) ? D2 + 64 : 1];
+    __shared__ uint32_t fsl[BYTES ? 1 : EW];   // staging slot: the enumerating node's next ensemble
+    extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
+
+    const Dyn lay = dyn_layout(KIND, a.bmax);
+    unsigned long long *const s_sum = (unsigned long long *)(dyn + lay.sum);
+    uint32_t *const VT = (uint32_t *)(dyn + lay.vt);    // region starts in enumeration order, end at [nb]
+    uint32_t *const SX = (uint32_t *)(dyn + lay.sx);    // region start addresses (start+length streams)
+    uint32_t *const CX = (uint32_t *)(dyn + lay.cx);    // per-parent context
+    uint32_t *const s_cnt = (uint32_t *)(dyn + lay.cnt);
+    uint32_t *const s_min = (uint32_t *)(dyn + lay.mn);
+    uint32_t *const s_max = (uint32_t *)(dyn + lay.mx);
 
     const uint32_t t = threadIdx.x;
-    const uint32_t wv = t >> 6;
-    const uint32_t ring_base = lds_addr(ring);
-    constexpr uint32_t R = G::R;
-    // A single-wave processor needs no hardware barrier: a wave's LDS operations complete in
-    // order, so only the compiler must be kept from moving memory accesses across this point.
-    auto sync = [&]() {
-        if constexpr (W == 64) asm volatile("" ::: "memory");
-        else bar();
-    };
 
     // stage parameters
     const uint32_t modm = a.param[0] ? a.param[0] : 4u;
@@ -384,7 +228,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
     const bool mod_pow2 = (modm & (modm - 1u)) == 0u;
 
     // launches completed so far, as a 24-bit tag in [1, 2^24 - 1] for the look-back words
-    // (the control block only changes after every workgroup of a launch has finished)
+    // (the control block only changes after every wave of a launch has finished)
     const uint32_t epoch_tag =
         uni(__hip_atomic_load(&a.ctl[CTL_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) % 0xFFFFFFu + 1u;
 
@@ -408,7 +252,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         const uint32_t nb = min(B, sd.n_parents - p0);
 #pragma unroll
         for (uint32_t q = 0; q < R; ++q) {
-            const uint32_t i = q * W + t;
+            const uint32_t i = q * 64u + t;
             if constexpr (!BYTES) {
                 if (i <= nb) r.off[q] = sd.offsets[p0 + i];
             } else {
@@ -422,67 +266,72 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
             }
         }
     };
+    auto take_claim = [&]() -> uint32_t {
+        uint32_t c = 0;
+        if (t == 0) c = atomicAdd(&a.ctl[CTL_CLAIM], 1u);
+        return uni(c);
+    };
 
     // claims are taken two ahead: g is worked on, g1 is next (its region table in registers)
-    uint32_t first = 0, second = 0;
-    if (t == 0) {
-        first = atomicAdd(&a.ctl[CTL_CLAIM], 1u);
-        second = atomicAdd(&a.ctl[CTL_CLAIM], 1u);
-        misc[M_NEXT] = first;
-        misc[M_NEXT + 1] = second;
-    }
-    sync();
-    uint32_t g = uni(misc[M_NEXT]);
-    uint32_t g1 = uni(misc[M_NEXT + 1]);
+    uint32_t g = take_claim();
+    uint32_t g1 = take_claim();
     ClaimRegs<R> cur;
     load_claim(g, cur);
-    sync();
 
     while (g < a.total_claims) {
-        uint32_t g_next = 0;
-        if (t == 0) g_next = atomicAdd(&a.ctl[CTL_CLAIM], 1u);   // the claim after g1
+        const uint32_t g_next = take_claim();   // the claim after g1
         ClaimRegs<R> nxt;
-        load_claim(g1, nxt);                                      // consumed at the next claim
+        load_claim(g1, nxt);                    // consumed at the next claim
 
         const StreamDev &sd = a.streams[stream_of(g)];
-        const uint8_t *elems = (const uint8_t *)sd.elements;
+        const uint8_t *const elems = (const uint8_t *)sd.elements;
         const uint32_t B = sd.parents_per_claim;
         const uint32_t cidx = g - sd.claim_begin;
         const uint32_t p0 = cidx * B;
         const uint32_t nb = uni(min(B, sd.n_parents - p0));
-        const uint32_t nbytes_total = sd.n_elements * EB;
 
         // ---- region table of the claim (enumeration: findCount per parent)
         uint32_t vbeg, vend;
         if constexpr (!BYTES) {
 #pragma unroll
             for (uint32_t q = 0; q < R; ++q) {
-                const uint32_t i = q * W + t;
+                const uint32_t i = q * 64u + t;
                 if (i <= nb) VT[i] = cur.off[q];
                 if constexpr (CTXP)
                     if (i < nb) CX[i] = cur.ctx[q];
             }
-            sync();
+            order();
             vbeg = uni(VT[0]);
             vend = uni(VT[nb]);
         } else {
+            // enumeration positions of the lines: exclusive prefix of their lengths
             uint32_t carry = 0;
 #pragma unroll
             for (uint32_t q = 0; q < R; ++q) {
-                const uint32_t i = q * W + t;
-                if (i < nb) SX[i] = cur.off[q];
-                uint32_t tot;
-                const uint32_t ex = wg_scan_u32<W>(i < nb ? cur.len[q] : 0u, misc, tot);
-                if (i < nb) VT[i] = carry + ex;
-                carry += tot;
-                sync();
+                const uint32_t i = q * 64u + t;
+                const uint32_t len = i < nb ? cur.len[q] : 0u;
+                uint32_t inc = len;
+#pragma unroll
+                for (uint32_t o = 1; o < 64; o <<= 1) {
+                    const uint32_t u = __shfl_up(inc, o, 64);
+                    if (t >= o) inc += u;
+                }
+                if (i < nb) {
+                    SX[i] = cur.off[q];
+                    VT[i] = carry + inc - len;
+                }
+                carry += uni(__shfl(inc, 63, 64));
             }
             if (t == 0) VT[nb] = carry;
-            sync();
+            order();
             vbeg = 0;
             vend = carry;
+            if constexpr (TAG) {   // lines are enumerated over the claim's byte address range
+                vbeg = nb ? uni(SX[0]) : 0u;
+                vend = nb ? uni(SX[nb - 1] + (VT[nb] - VT[nb - 1])) : 0u;
+            }
         }
-        for (uint32_t i = t; i < nb; i += W) {
+        for (uint32_t i = t; i < nb; i += 64u) {
             s_cnt[i] = 0;
             s_sum[i] = 0ull;
             s_min[i] = 0xFFFFFFFFu;
@@ -493,7 +342,7 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
         // is read; a malformed stream is flagged and its claims are skipped.
         {
             bool bad = false;
-            for (uint32_t i = t; i < nb; i += W) {
+            for (uint32_t i = t; i < nb; i += 64u) {
                 if constexpr (!BYTES) {
                     bad |= (VT[i] > VT[i + 1]) || (i + 1u == nb && VT[nb] > sd.n_elements);
                 } else {
@@ -502,105 +351,46 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                     bad |= end > lim;
                 }
             }
-            if (t == 0) misc[M_BAD] = 0;
-            sync();
-            if (bad) misc[M_BAD] = 1;
-            sync();
-            if (uni(misc[M_BAD])) {
+            if (__ballot(bad)) {
                 if (t == 0) {
                     atomicOr((unsigned int *)&sd.stats[ST_ERROR], 1u);
                     if (a.emit_outputs)   // successors of this claim must not wait for it
                         __hip_atomic_store(&sd.lookback[cidx], ((unsigned long long)epoch_tag << 40) | (2ull << 38),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    misc[M_NEXT] = g_next;
                 }
-                sync();
+                order();
                 g = g1;
-                g1 = uni(misc[M_NEXT]);
+                g1 = g_next;
                 cur = nxt;
                 continue;
             }
         }
 
-        // ---- element ring: the claim's byte range, chunked from a 16-byte aligned base
-        uint32_t b0, b1;
-        if constexpr (!BYTES) {
-            b0 = vbeg * 4u;
-            b1 = vend * 4u;
-        } else {
-            b0 = nb ? uni(SX[0]) : 0u;
-            b1 = nb ? uni(SX[nb - 1] + (VT[nb] - VT[nb - 1])) : 0u;
-            if constexpr (TAG) {   // lines are enumerated over the claim's address range
-                vbeg = b0;
-                vend = b1;
-            }
-        }
-        const uint32_t A0 = b0 & ~15u;
-        const uint32_t nch = (b1 > b0) ? (b1 - A0 + G::CHB - 1u) / G::CHB : 0u;
-        uint32_t ld_next = 0, ld_ready = 0;
-        uint32_t partial_mask = 0;   // per lane: ring slots holding a partial tail block to patch
-
-        auto issue = [&]() {
-            const uint32_t c = ld_next;
-            const uint32_t blk = A0 + c * G::CHB + t * 16u;
-            const bool full = blk + 16u <= nbytes_total;
-            const uint8_t *src = full ? elems + blk : (const uint8_t *)a.dummy;
-            if (!full && blk < nbytes_total) partial_mask |= 1u << (c % G::NS);
-            __builtin_amdgcn_global_load_lds((glb_void_t *)src,
-                                             (lds_void_t *)(ring + (c % G::NS) * G::CHB + wv * 1024u), 16, 0, 0);
-            ld_next = c + 1u;
-        };
-        // make chunks [0, k] readable
-        auto ready_upto = [&](uint32_t k) {
-            while (ld_ready <= k) {
-                wait_vm_n(ld_next - 1u - ld_ready);
-                if (partial_mask & (1u << (ld_ready % G::NS))) {
-                    partial_mask &= ~(1u << (ld_ready % G::NS));
-                    const uint32_t blk = A0 + ld_ready * G::CHB + t * 16u;
-                    const uint32_t dst = ring_base + (ld_ready % G::NS) * G::CHB + t * 16u;
-                    for (uint32_t k2 = 0; blk + k2 < nbytes_total; ++k2) ring_w8(dst + k2, elems[blk + k2]);
-                }
-                sync();
-                ++ld_ready;
-            }
-        };
-        // issue every chunk whose ring slot is free: chunk ld_next reuses the slot of
-        // chunk ld_next - NS, which must end at or before need_from
-        auto refill = [&](uint32_t need_from) {
-            while (ld_next < nch && (ld_next < G::NS || A0 + (ld_next - G::NS + 1u) * G::CHB <= need_from)) issue();
-        };
-        auto ring_off = [&](uint32_t addr) -> uint32_t { return ring_base + ((addr - A0) & (G::RING - 1u)); };
-        auto ring_drain = [&]() {
-            if (ld_ready < ld_next) {   // chunks issued beyond what was read (look-ahead margin)
-                wait_vm<0>();
-                sync();
-            }
-            ld_next = 0;
-            ld_ready = 0;
-            partial_mask = 0;
-        };
-        // Make the bytes of the enumerating node's next ensemble (fpos, e items) readable:
-        // one byte before it (word starts look back) and, for the text kind, a look-ahead
-        // margin for the word-length node.  False only on an internal logic error.
-        auto f_stage = [&](uint32_t fpos_, uint32_t fj_, uint32_t e) -> bool {
-            if (!e) return true;
-            uint32_t need_lo, need_hi;
+        // ---- element access
+        // text: the whole byte array (addresses fit in 32 bits); word loads near its end fall
+        // back to bytes, so no load depends on the range check for its value
+        const __amdgpu_buffer_rsrc_t rtext = rsrc(elems, BYTES ? sd.n_elements : 0u);
+        // u32 elements: the ensemble at position pos is copied to the staging slot by direct
+        // buffer->LDS loads (item k*64 + lane to word k*64 + lane; positions past vend read as
+        // zero).  The copy is issued as soon as the slot's previous contents have been taken, so
+        // it overlaps the downstream firings; its completion is awaited explicitly.
+        uint32_t staged = 0xFFFFFFFFu;   // position whose ensemble the slot holds or is receiving
+        auto stage = [&](uint32_t pos) {
             if constexpr (!BYTES) {
-                need_lo = fpos_ * 4u;
-                need_hi = (fpos_ + e) * 4u;
-            } else {
-                const uint32_t adr0 = TAG ? fpos_ : uni(SX[fj_]) + (fpos_ - uni(VT[fj_]));
-                need_lo = adr0 > A0 ? adr0 - 1u : A0;
-                need_hi = adr0 + e + 64u;
-                if (need_hi > b1) need_hi = b1;
+                if (pos < vend) {
+                    const __amdgpu_buffer_rsrc_t r = rsrc(elems + (size_t)pos * 4u, min(EW, vend - pos) * 4u);
+                    stage_rounds<0, V>(r, (lds_void_t *)fsl, t * 4u);
+                    staged = pos;
+                }
             }
-            refill(need_lo);
-            const uint32_t last_chunk = (need_hi - 1u - A0) / G::CHB;
-            // one ensemble spans far less than NS-1 chunks, so refill has issued it
-            if (ld_next <= last_chunk) return false;
-            ready_upto(last_chunk);
-            return true;
         };
+        // u32 elements outside the staged path (the output-count pass): plain buffer loads
+        auto load_ens = [&](uint32_t pos, uint32_t n, uint32_t (&x)[V]) {
+            const __amdgpu_buffer_rsrc_t r = rsrc(elems + (size_t)pos * 4u, n * 4u);
+#pragma unroll
+            for (int k = 0; k < V; ++k) x[k] = __builtin_amdgcn_raw_buffer_load_b32(r, (k * 64 + t) * 4, 0, 0);
+        };
+
         // Region of enumeration position v (tag strategy): the largest j whose start is <= v,
         // by element index (CSR) or by byte address (lines), searching from jlo_.
         auto f_region = [&](uint32_t v, uint32_t jlo_) -> uint32_t {
@@ -612,121 +402,104 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
             }
             return l2;
         };
-        // The enumerating node for one firing: items fpos + k*W + lane, k < V, of which the
-        // first e are real.  Fetches each element under its parent's context and applies the
-        // first stage.  keep[k], item[k], aux[k], reg[k] describe item k of this lane.
-        auto f_fire = [&](uint32_t fpos_, uint32_t fj_, uint32_t jlo_, uint32_t e, uint32_t (&keep)[V],
-                          uint32_t (&item)[V], uint32_t (&aux)[V], uint32_t (&reg)[V]) {
-            uint32_t jr = jlo_;
+        // Regions of the items fpos_ + k*64 + lane (tag strategy; the first e are real).  jlo_ is
+        // the region of the first item; one_ says every item lies in it.
+        auto f_regions = [&](auto full, uint32_t fpos_, uint32_t e, uint32_t jlo_, bool one_, uint32_t (&reg)[V]) {
+            constexpr bool FULL = decltype(full)::value;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                keep[k] = 0;
-                aux[k] = 0;
-                const uint32_t i = (uint32_t)k * W + t;
-                const uint32_t v = fpos_ + (i < e ? i : 0u);
-                if constexpr (TAG) {
-                    jr = (i < e) ? f_region(v, jr) : jr;
-                    reg[k] = jr;
+                const uint32_t i = (uint32_t)k * 64u + t;
+                if (one_) {
+                    reg[k] = jlo_;
                 } else {
-                    reg[k] = fj_;
+                    jlo_ = f_region(fpos_ + (FULL || i < e ? i : 0u), jlo_);   // positions grow with k
+                    reg[k] = jlo_;
                 }
             }
+        };
+        // The first stage on item i = k*64 + lane of an ensemble at fpos_: whether it passes,
+        // the value it carries on, and the hash kind's child count.  x is the element (u32
+        // kinds); j the item's region, ls_/lv_ its line's address and position (text).
+        auto f_item = [&](uint32_t i, bool act, uint32_t fpos_, uint32_t x, uint32_t j, uint32_t thr, uint32_t ls_,
+                          uint32_t lv_, uint32_t &item, uint32_t &aux) -> bool {
+            aux = 0;
             if constexpr (!BYTES) {
-                uint32_t addr[V], x[V];
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const uint32_t i = (uint32_t)k * W + t;
-                    addr[k] = ring_off((fpos_ + (i < e ? i : 0u)) * 4u);
+                item = x;
+                bool kp;
+                if constexpr (KIND == RS_MODFILTER) {
+                    kp = mod_pow2 ? ((x & (modm - 1u)) == modr) : (x % modm == modr);
+                } else if constexpr (KIND == RS_HASH_EXPAND) {
+                    const uint32_t h = fmix32(x ^ salt_key(0));
+                    kp = h & 1u;
+                    aux = (h >> 1) & 3u;
+                } else {
+                    kp = x < (TAG ? CX[j] : thr);
                 }
-                ring_read<V>(addr, x);
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const bool act = (uint32_t)k * W + t < e;
-                    item[k] = x[k];
-                    if constexpr (KIND == RS_MODFILTER) {
-                        keep[k] = act && (mod_pow2 ? ((x[k] & (modm - 1u)) == modr) : (x[k] % modm == modr));
-                    } else if constexpr (KIND == RS_HASH_EXPAND) {
-                        const uint32_t h = fmix32(x[k] ^ salt_key(0));
-                        keep[k] = act && (h & 1u);
-                        aux[k] = (h >> 1) & 3u;
-                    } else {
-                        keep[k] = act && x[k] < CX[reg[k]];
-                    }
-                }
+                return act && kp;
             } else {
-                uint32_t ab[2 * V], bv[2 * V];
-                bool in_line[V], at_start[V];
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const uint32_t i = (uint32_t)k * W + t;
-                    const uint32_t v = fpos_ + i;
-                    const uint32_t j = reg[k];
-                    // signal: v is VT[j] plus the line-relative position; tag: v is the address
-                    const uint32_t ls = SX[j];
-                    const uint32_t adr = TAG ? v : ls + (v - VT[j]);
-                    item[k] = adr;
-                    in_line[k] = i < e && (!TAG || adr < ls + (VT[j + 1] - VT[j]));
-                    at_start[k] = adr == ls;
-                    ab[2 * k] = in_line[k] ? ring_off(adr) : ring_base;
-                    ab[2 * k + 1] = (in_line[k] && !at_start[k]) ? ring_off(adr - 1u) : ring_base;
-                }
-                ring_read_u8<2 * V>(ab, bv);
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const uint32_t prev = at_start[k] ? 32u : bv[2 * k + 1];
-                    keep[k] = in_line[k] && (bv[2 * k] != 32u) && (prev == 32u);
-                }
+                // signal: the line's address plus the line-relative position; tag: the address
+                const uint32_t ls = TAG ? SX[j] : ls_;
+                const uint32_t adr = TAG ? fpos_ + i : ls_ + (fpos_ - lv_) + i;
+                item = adr;
+                const bool in_line = act && (!TAG || adr < ls + (VT[j + 1] - VT[j]));
+                const bool at_start = adr == ls;
+                const uint32_t cb = __builtin_amdgcn_raw_buffer_load_b8(rtext, in_line ? adr : 0u, 0, 0);
+                const uint32_t pb = __builtin_amdgcn_raw_buffer_load_b8(rtext, adr - (at_start ? 0u : 1u), 0, 0);
+                const uint32_t prev = at_start ? 32u : pb;
+                return in_line && cb != 32u && prev == 32u;
             }
         };
 
         bool failed = false;
         // ---- ordered output stream: count this claim's outputs, then learn its base from the
         // claims before it (decoupled look-back over the stream's claims) before producing.
-        uint32_t out_base_lo = 0, out_base_hi = 0;
+        unsigned long long out_rank = 0;
         if (a.emit_outputs) {
-            refill(A0);
             uint32_t fpos = vbeg, fj = 0, jlo = 0;
             bool fdone = TAG ? (vbeg >= vend) : (nb == 0);
             unsigned long long n_out = 0;
             while (!fdone) {
-                const uint32_t e = TAG ? min(EW, vend - fpos) : min(EW, uni(VT[fj + 1]) - fpos);
-                if (!f_stage(fpos, fj, e)) {
-                    failed = true;
-                    break;
-                }
-                uint32_t keep[V], item[V], aux[V], reg[V], nout[V], off[V], tot;
-                f_fire(fpos, fj, jlo, e, keep, item, aux, reg);
+                const uint32_t rend = TAG ? vend : uni(VT[fj + 1]);
+                const uint32_t e = min(EW, rend - fpos);
+                if (e) {
+                    const uint32_t ls = BYTES ? uni(SX[fj]) : 0u, lv = BYTES ? uni(VT[fj]) : 0u;
+                    const uint32_t thr = (CTXP && !TAG) ? uni(CX[fj]) : 0u;
+                    uint32_t reg[V], x[V];
+                    if constexpr (TAG) f_regions(BoolC<false>{}, fpos, e, jlo, false, reg);
+                    if constexpr (!BYTES) load_ens(fpos, e, x);
 #pragma unroll
-                for (int k = 0; k < V; ++k) nout[k] = keep[k] ? (KIND == RS_HASH_EXPAND ? aux[k] : 1u) : 0u;
-                ens_scan<W, V, true>(nout, off, tot, misc);
-                n_out += tot;
-                if constexpr (TAG) {
+                    for (int k = 0; k < V; ++k) {
+                        const uint32_t i = (uint32_t)k * 64u + t;
+                        uint32_t item, aux;
+                        const uint32_t j = TAG ? reg[k] : fj;
+                        const bool keep = f_item(i, i < e, fpos, BYTES ? 0u : x[k], j, thr, ls, lv, item, aux);
+                        const uint32_t nout = keep ? (KIND == RS_HASH_EXPAND ? aux : 1u) : 0u;
+                        n_out += (uint32_t)__popcll(__ballot(nout & 1u)) + 2u * (uint32_t)__popcll(__ballot(nout & 2u));
+                    }
+                    if constexpr (TAG) {
+                        const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
 #pragma unroll
-                    for (int k = 0; k < V; ++k)
-                        if ((uint32_t)k * W + t == e - 1u) misc[M_JLAST] = reg[k];
-                }
-                fpos += e;
-                sync();
-                if constexpr (TAG) {
-                    jlo = uni(misc[M_JLAST]);
-                    fdone = (fpos == vend);
-                } else {
-                    if (fpos == uni(VT[fj + 1])) {
-                        ++fj;
-                        fdone = (fj == nb);
+                        for (int k = 0; k < V; ++k)
+                            if ((uint32_t)k == kl) jlo = __builtin_amdgcn_readlane(reg[k], ll);
                     }
                 }
+                fpos += e;
+                if constexpr (TAG) {
+                    fdone = (fpos == vend);
+                } else if (fpos == rend) {
+                    ++fj;
+                    fdone = (fj == nb);
+                }
             }
-            ring_drain();
             // look-back: words are (epoch tag << 40) | (flag << 38) | value, flag 1 = this claim's
             // own count, flag 2 = inclusive prefix through this claim
+            unsigned long long prefix = 0;
             if (t == 0) {
                 unsigned long long *lb = sd.lookback;
                 const unsigned long long tagw = (unsigned long long)epoch_tag << 40;
                 const unsigned long long mask38 = (1ull << 38) - 1ull;
                 __hip_atomic_store(&lb[cidx], tagw | (1ull << 38) | (n_out & mask38), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-                unsigned long long prefix = 0;
                 for (uint32_t i = cidx; i-- > 0;) {
                     unsigned long long w;
                     for (;;) {
@@ -739,43 +512,250 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                 }
                 __hip_atomic_store(&lb[cidx], tagw | (2ull << 38) | ((prefix + n_out) & mask38), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-                misc[M_BASE_LO] = (uint32_t)prefix;
-                misc[M_BASE_HI] = (uint32_t)(prefix >> 32);
             }
-            sync();
-            out_base_lo = uni(misc[M_BASE_LO]);
-            out_base_hi = uni(misc[M_BASE_HI]);
+            out_rank = ((unsigned long long)uni((uint32_t)(prefix >> 32)) << 32) | uni((uint32_t)prefix);
         }
         uint32_t *const out_items = sd.out_items;
-        unsigned long long out_rank = ((unsigned long long)out_base_hi << 32) | out_base_lo;
-
-        refill(A0);
 
         // ---- node state (all uniform)
-        uint32_t h1 = 0, t1 = 0, sh1 = 0, st1 = 0;
-        uint32_t h2 = 0, t2 = 0, sh2 = 0, st2 = 0;
+        uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;            // data queue heads and tails
+        uint32_t sh1 = 0, st1 = 0, sh2 = 0, st2 = 0;        // signal queue heads and tails
+        uint32_t sq1 = 0, sq2 = 0;                          // signal queues (entry n in lane n mod 64)
         // enumerating node: signal strategy walks region fj at position fpos;
         // tag strategy walks ensembles of EW consecutive positions from fpos.
-        uint32_t fj = 0, fpos = vbeg, jlo = 0, ej = 0;
+        uint32_t fj = 0, fpos = vbeg, jlo = 0;
+        uint32_t rend = 0, ls = 0, lv = 0;                  // current region's end, line address, line position
+        if constexpr (!TAG) {
+            if (nb) {
+                rend = uni(VT[1]);
+                if constexpr (BYTES) ls = uni(SX[0]);
+            }
+        }
         bool fdone = TAG ? (vbeg >= vend) : (nb == 0);
-        uint32_t a_items = 0;                 // items aggregated since the last signal (signal strategy)
+        uint32_t ej = 0;                      // signal strategy: region E is in
+        uint32_t ja = 0, a_items = 0;         // signal strategy: region A closes next, items it has taken
         Acc acc;
         acc_reset(acc);
-        uint32_t acc_tag = 0xFFFFFFFFu;       // tag strategy: region of this lane's running accumulator
-        uint64_t st_fire[3] = {0, 0, 0}, st_items[3] = {0, 0, 0}, st_full[3] = {0, 0, 0}, st_sig[3] = {0, 0, 0};
+        uint32_t utag = 0;                    // tag strategy: region every lane's accumulator belongs to
+        // lane n counts statistic n of this claim: firings, items, full firings and signals per node
+        uint32_t stv = 0;
+        auto stat = [&](uint32_t n, uint32_t v) { stv += (t == n) ? v : 0u; };
         // every scheduler iteration fires a node; a claim needs at most a few firings per
         // element and per region, so this bound only trips on a scheduling error
-        const unsigned long long iter_cap = 8ull * ((unsigned long long)(vend - vbeg) + nb) + 64ull;
-        unsigned long long iters = 0;
+        const uint32_t iter_cap =
+            (uint32_t)min(8ull * ((unsigned long long)(vend - vbeg) + nb) + 64ull, 0xFFFFFFFFull);
+        uint32_t iters = 0;
 
-        auto flush_tag = [&]() {
+        stage(fpos);
+
+        // per-lane flush of the accumulator into region slot j (LDS atomics)
+        auto flush_lane = [&](uint32_t j) {
             if (acc.cnt) {
-                atomicAdd(&s_cnt[acc_tag], acc.cnt);
-                atomicAdd(&s_sum[acc_tag], acc.sum);
-                atomicMin(&s_min[acc_tag], acc.mn);
-                atomicMax(&s_max[acc_tag], acc.mx);
-                acc_reset(acc);
+                atomicAdd(&s_cnt[j], acc.cnt);
+                atomicAdd(&s_sum[j], acc.sum);
+                atomicMin(&s_min[j], acc.mn);
+                atomicMax(&s_max[j], acc.mx);
             }
+            acc_reset(acc);
+        };
+        // whole-wave flush of accumulators that all belong to region j
+        auto flush_wave = [&](uint32_t j) {
+            const Acc r = wave_reduce(acc);
+            if (t == 0 && r.cnt) {
+                atomicAdd(&s_cnt[j], r.cnt);
+                atomicAdd(&s_sum[j], r.sum);
+                atomicMin(&s_min[j], r.mn);
+                atomicMax(&s_max[j], r.mx);
+            }
+            acc_reset(acc);
+        };
+
+        // ---------------- A: the aggregating node, one firing of e items from its queue head
+        auto a_fire = [&](auto full, uint32_t e) {
+            constexpr bool FULL = decltype(full)::value;
+            const uint32_t hq = HAS_E ? h2 : h1;
+            const uint32_t *qv = HAS_E ? q2v : q1v;
+            const uint8_t *qt = HAS_E ? q2t : q1t;
+            uint32_t y[V], tg[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const uint32_t pos = (hq + (uint32_t)k * 64u + t) & (DA - 1u);
+                y[k] = qv[pos];
+                if constexpr (TAG) tg[k] = qt[pos]; else tg[k] = 0u;
+            }
+            uint32_t tf = 0, tl = 0;
+            if constexpr (TAG) {
+                tf = uni(qt[hq & (DA - 1u)]);
+                tl = uni(qt[(hq + e - 1u) & (DA - 1u)]);
+            }
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                // the expansion's children arrive as pre-images x ^ K(j+1); finishing the hash
+                // here completes H(x, j+1)
+                if constexpr (KIND == RS_HASH_EXPAND) y[k] = fmix32(y[k]);
+            }
+            if (out_items) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const uint32_t i = (uint32_t)k * 64u + t;
+                    if (FULL || i < e) out_items[out_rank + i] = y[k];   // serial order
+                }
+            }
+            if (!TAG || tf == tl) {
+                if constexpr (TAG) {
+                    if (tf != utag) {   // every lane's accumulator closes together
+                        flush_wave(utag);
+                        utag = tf;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < V; ++k) acc_add(acc, y[k], FULL || (uint32_t)k * 64u + t < e);
+            } else {
+                // the ensemble crosses region boundaries: each lane flushes where its own items
+                // change region (tags grow along the queue), then every lane flushes at the end
+                uint32_t lt = utag;
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const bool act = FULL || (uint32_t)k * 64u + t < e;
+                    if (act && tg[k] != lt) {
+                        flush_lane(lt);
+                        lt = tg[k];
+                    }
+                    acc_add(acc, y[k], act);
+                }
+                flush_lane(lt);
+                utag = tl;
+            }
+            if constexpr (HAS_E) h2 += e; else h1 += e;
+            a_items += e;
+            out_rank += e;
+            stat(ST_FIRINGS + 2, 1u);
+            stat(ST_ITEMS + 2, e);
+            if constexpr (FULL) stat(ST_FULL + 2, 1u);
+        };
+
+        // ---------------- E: the second node, one firing of e items from q1's head
+        auto e_fire = [&](auto full, uint32_t e) {
+            constexpr bool FULL = decltype(full)::value;
+            uint32_t x[V], c[V], tg[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const uint32_t pos = (h1 + (uint32_t)k * 64u + t) & (D1 - 1u);
+                x[k] = q1v[pos];
+                if constexpr (KIND == RS_HASH_EXPAND) c[k] = q1a[pos]; else c[k] = 1u;
+                if constexpr (TAG) tg[k] = q1t[pos]; else tg[k] = 0u;
+            }
+            if constexpr (BYTES) {
+                // word length: run of non-space bytes from the word's start, within its line,
+                // four bytes at a time
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    if (!(FULL || (uint32_t)k * 64u + t < e)) continue;
+                    const uint32_t j = TAG ? tg[k] : ej;
+                    const uint32_t le = SX[j] + (VT[j + 1] - VT[j]);
+                    uint32_t p = x[k];
+                    while (p < le) {
+                        const uint32_t q = p & ~3u;
+                        uint32_t word = 0;
+                        if (q + 8u <= sd.n_elements) {
+                            const uint32_t w0 = __builtin_amdgcn_raw_buffer_load_b32(rtext, q, 0, 0);
+                            const uint32_t w1 = __builtin_amdgcn_raw_buffer_load_b32(rtext, q + 4u, 0, 0);
+                            word = __builtin_amdgcn_alignbyte(w1, w0, p & 3u);
+                        } else {
+                            for (uint32_t b = 0; b < 4u && p + b < le; ++b)
+                                word |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rtext, p + b, 0, 0) << (8u * b);
+                        }
+                        // first space among the four bytes: lowest zero byte of word ^ "    "
+                        const uint32_t z = word ^ 0x20202020u;
+                        const uint32_t zm = (z - 0x01010101u) & ~z & 0x80808080u;
+                        uint32_t step = zm ? ((uint32_t)__builtin_ctz(zm) >> 3) : 4u;
+                        if (le - p < step) step = le - p;
+                        p += step;
+                        if (step < 4u) break;
+                    }
+                    x[k] = p - x[k];
+                }
+            }
+            uint32_t run = 0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const bool act = FULL || (uint32_t)k * 64u + t < e;
+                const uint32_t nout = act ? c[k] : 0u;
+                const uint64_t b0 = __ballot(nout & 1u);
+                uint32_t within = rank_below(b0), pc = (uint32_t)__popcll(b0);
+                if constexpr (KE == 3u) {
+                    const uint64_t b1 = __ballot(nout & 2u);
+                    within += 2u * rank_below(b1);
+                    pc += 2u * (uint32_t)__popcll(b1);
+                }
+                const uint32_t base = t2 + run + within;
+#pragma unroll
+                for (uint32_t ch = 0; ch < KE; ++ch) {
+                    const uint32_t pos = ch < nout ? ((base + ch) & (D2 - 1u)) : D2 + t;
+                    // child ch of x leaves as its pre-image x ^ K(ch+1) (hash kind); a word as its length
+                    q2v[pos] = KIND == RS_HASH_EXPAND ? x[k] ^ salt_key(ch + 1u) : x[k];
+                    if constexpr (TAG) q2t[pos] = (uint8_t)tg[k];
+                }
+                run += pc;
+            }
+            h1 += e;
+            t2 += run;
+            stat(ST_FIRINGS + 1, 1u);
+            stat(ST_ITEMS + 1, e);
+            if constexpr (FULL) stat(ST_FULL + 1, 1u);
+        };
+
+        // ---------------- F: the enumerating node, one firing of e items from fpos
+        auto f_node = [&](auto full, uint32_t e) {
+            constexpr bool FULL = decltype(full)::value;
+            bool one = true;
+            if constexpr (TAG) one = jlo + 1u >= nb || uni((BYTES ? SX : VT)[jlo + 1u]) > fpos + e - 1u;
+            uint32_t reg[V], x[V];
+            if constexpr (TAG) {
+                f_regions(full, fpos, e, jlo, one, reg);
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; ++k) reg[k] = fj;
+            }
+            if constexpr (!BYTES) {
+                if (staged != fpos) stage(fpos);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the staged copy has landed
+#pragma unroll
+                for (int k = 0; k < V; ++k) x[k] = fsl[k * 64 + t];
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; ++k) x[k] = 0;
+            }
+            const uint32_t thr = (CTXP && !TAG) ? uni(CX[fj]) : 0u;
+            uint32_t run = 0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const uint32_t i = (uint32_t)k * 64u + t;
+                uint32_t item, aux;
+                const bool keep = f_item(i, FULL || i < e, fpos, x[k], reg[k], thr, ls, lv, item, aux);
+                const uint64_t b = __ballot(keep);
+                const uint32_t within = rank_below(b), pc = (uint32_t)__popcll(b);
+                // dropped lanes write spill slots on the banks the kept ones leave free
+                const uint32_t pos = keep ? ((t1 + run + within) & (D1 - 1u)) : D1 + ((t1 + run + pc + t - within) & 63u);
+                q1v[pos] = item;
+                if constexpr (KIND == RS_HASH_EXPAND) q1a[pos] = (uint8_t)aux;
+                if constexpr (TAG) q1t[pos] = (uint8_t)reg[k];
+                run += pc;
+            }
+            if constexpr (TAG) {
+                if (!one) {
+                    const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
+#pragma unroll
+                    for (int k = 0; k < V; ++k)
+                        if ((uint32_t)k == kl) jlo = __builtin_amdgcn_readlane(reg[k], ll);
+                }
+            }
+            stage(fpos + e);   // the slot's contents are in registers: load the next ensemble
+            t1 += run;
+            fpos += e;
+            stat(ST_FIRINGS + 0, 1u);
+            stat(ST_ITEMS + 0, e);
+            if constexpr (FULL) stat(ST_FULL + 0, 1u);
         };
 
         for (;;) {
@@ -783,296 +763,138 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
                 failed = true;
                 break;
             }
-            // ---------------- A: the aggregating node (drains first)
+            // ---------------- A (drains first)
             {
-                uint32_t &h = HAS_E ? h2 : h1;
-                uint32_t &sh = HAS_E ? sh2 : sh1;
-                const uint32_t tq = HAS_E ? t2 : t1;
-                const uint32_t stq = HAS_E ? st2 : st1;
-                const uint32_t *qv = HAS_E ? q2v : q1v;
-                const uint16_t *qt = HAS_E ? q2t : q1t;
-                const uint32_t *sp = HAS_E ? sp2 : sp1;
-                constexpr uint32_t D = HAS_E ? G::D2 : G::D1;
-                const bool up_done = HAS_E ? (fdone && h1 == t1) : fdone;
+                const uint32_t hq = HAS_E ? h2 : h1, tq = HAS_E ? t2 : t1;
                 uint32_t e = 0;
                 bool fire = false;
-                if (!TAG && sh < stq) {
-                    const uint32_t credit = uni(sp[sh & (G::SQ - 1u)]) - h;
-                    e = credit < EW ? credit : EW;
-                    fire = true;
-                } else {
-                    const uint32_t n = tq - h;
-                    if (n >= EW) {
-                        e = EW;
-                        fire = true;
-                    } else if (up_done && n > 0) {
-                        e = n;
-                        fire = true;
-                    }
-                }
-                if (fire) {
-                    if (e) {
-#pragma unroll
-                        for (int k = 0; k < V; ++k) {
-                            const uint32_t i = (uint32_t)k * W + t;
-                            if (i < e) {
-                                const uint32_t pos = (h + i) & (D - 1u);
-                                uint32_t y = qv[pos];
-                                // the expansion's children arrive as pre-images x ^ K(j+1);
-                                // finishing the hash here completes H(x, j+1)
-                                if constexpr (KIND == RS_HASH_EXPAND) y = fmix32(y);
-                                if (out_items) out_items[out_rank + i] = y;   // serial order
-                                if constexpr (TAG) {
-                                    const uint32_t tg = qt[pos];
-                                    if (tg != acc_tag) {
-                                        flush_tag();
-                                        acc_tag = tg;
-                                    }
-                                }
-                                acc_add(acc, y);
-                            }
-                        }
-                        h += e;
-                        a_items += e;
-                        out_rank += e;
-                        st_fire[2] += 1;
-                        st_items[2] += e;
-                        st_full[2] += (e == EW);
-                    }
-                    if constexpr (!TAG) {
-                        // signal phase: consume every slot that no item precedes
-                        while (sh < stq && uni(sp[sh & (G::SQ - 1u)]) == h) {
-                            const uint32_t j = uni(qv[h & (D - 1u)]);
+                if constexpr (!TAG) {
+                    uint32_t &sh = HAS_E ? sh2 : sh1;
+                    const uint32_t stq = HAS_E ? st2 : st1;
+                    if (sh < stq) {
+                        const uint32_t p = __builtin_amdgcn_readlane(HAS_E ? sq2 : sq1, sh & (SQ - 1u));
+                        if (p == hq) {
+                            // signal phase: no item precedes the signal, so region ja ends here
                             if (a_items) {
-                                const Acc r = wg_reduce<W>(acc, misc);
+                                const Acc r = wave_reduce(acc);
                                 if (t == 0) {
-                                    s_cnt[j] = r.cnt;
-                                    s_sum[j] = r.sum;
-                                    s_min[j] = r.mn;
-                                    s_max[j] = r.mx;
+                                    s_cnt[ja] = r.cnt;
+                                    s_sum[ja] = r.sum;
+                                    s_min[ja] = r.mn;
+                                    s_max[ja] = r.mx;
                                 }
                                 acc_reset(acc);
                                 a_items = 0;
                             }
-                            ++h;
+                            ++ja;
                             ++sh;
-                            st_sig[2] += 1;
+                            stat(ST_SIGNALS + 2, 1u);
+                            continue;
                         }
+                        e = min(p - hq, EW);   // the signal's credit bounds the ensemble
+                        fire = true;
                     }
-                    sync();
-                    continue;
                 }
-            }
-            // ---------------- E: the second node
-            if constexpr (HAS_E) {
-                uint32_t e = 0;
-                bool fire = false;
-                const uint32_t space = G::D2 - (t2 - h2) - (TAG ? 0u : 1u);
-                const uint32_t cap = space / KE;
-                if (!TAG && sh1 < st1) {
-                    const uint32_t credit = uni(sp1[sh1 & (G::SQ - 1u)]) - h1;
-                    e = min(min(credit, EW), cap);
-                    fire = (credit == 0) ? (space >= 1u && st2 - sh2 < G::SQ) : (e > 0);
-                } else {
-                    const uint32_t n = t1 - h1;
-                    if (n >= EW || (fdone && n > 0)) {
-                        e = min(min(n, EW), cap);
-                        fire = e > 0;
+                if (!fire) {
+                    const bool up_done = HAS_E ? (fdone && h1 == t1) : fdone;
+                    const uint32_t n = tq - hq;
+                    if (n >= EW || (up_done && n > 0)) {
+                        e = min(n, EW);
+                        fire = true;
                     }
                 }
                 if (fire) {
-                    if (e) {
-                        uint32_t nout[V], x[V], tg[V], off[V], tot;
-#pragma unroll
-                        for (int k = 0; k < V; ++k) {
-                            const uint32_t i = (uint32_t)k * W + t;
-                            nout[k] = 0;
-                            x[k] = 0;
-                            tg[k] = 0;
-                            if (i < e) {
-                                const uint32_t pos = (h1 + i) & (G::D1 - 1u);
-                                x[k] = q1v[pos];
-                                if constexpr (TAG) tg[k] = q1t[pos];
-                                if constexpr (KIND == RS_HASH_EXPAND) {
-                                    nout[k] = q1a[pos];
-                                } else {
-                                    // word length: run of non-space bytes from the start, within the line,
-                                    // read four bytes at a time from the ring (global memory outside it)
-                                    const uint32_t j = TAG ? tg[k] : ej;
-                                    const uint32_t le = SX[j] + (VT[j + 1] - VT[j]);
-                                    const uint32_t wlo = A0 + (ld_next > G::NS ? ld_next - G::NS : 0u) * G::CHB;
-                                    const uint32_t whi = A0 + ld_ready * G::CHB;
-                                    uint32_t p = x[k];
-                                    while (p < le) {
-                                        const uint32_t q = p & ~3u;
-                                        uint32_t word = 0;
-                                        if (q >= wlo && q + 8u <= whi) {
-                                            uint32_t w0, w1;
-                                            ring_u32x2(ring_off(q), ring_off(q + 4u), w0, w1);
-                                            word = __builtin_amdgcn_alignbyte(w1, w0, p & 3u);
-                                        } else {
-                                            for (uint32_t b = 0; b < 4u && p + b < le; ++b)
-                                                word |= (uint32_t)elems[p + b] << (8u * b);
-                                        }
-                                        // first space among the four bytes: zero byte of word ^ "    "
-                                        const uint32_t z = word ^ 0x20202020u;
-                                        const uint32_t zm = (z - 0x01010101u) & ~z & 0x80808080u;
-                                        uint32_t step = zm ? ((uint32_t)__builtin_ctz(zm) >> 3) : 4u;
-                                        if (le - p < step) step = le - p;
-                                        p += step;
-                                        if (step < 4u) break;
-                                    }
-                                    x[k] = p - x[k];
-                                    nout[k] = 1;
-                                }
-                            }
-                        }
-                        ens_scan<W, V, KE == 3>(nout, off, tot, misc);
-#pragma unroll
-                        for (int k = 0; k < V; ++k) {
-                            const uint32_t base = t2 + off[k];
-                            if constexpr (KIND == RS_HASH_EXPAND) {
-                                // child j of x leaves as its pre-image x ^ K(j+1)
-                                if (nout[k] > 0) q2v[base & (G::D2 - 1u)] = x[k] ^ salt_key(1);
-                                if (nout[k] > 1) q2v[(base + 1u) & (G::D2 - 1u)] = x[k] ^ salt_key(2);
-                                if (nout[k] > 2) q2v[(base + 2u) & (G::D2 - 1u)] = x[k] ^ salt_key(3);
-                                if constexpr (TAG) {
-                                    if (nout[k] > 0) q2t[base & (G::D2 - 1u)] = (uint16_t)tg[k];
-                                    if (nout[k] > 1) q2t[(base + 1u) & (G::D2 - 1u)] = (uint16_t)tg[k];
-                                    if (nout[k] > 2) q2t[(base + 2u) & (G::D2 - 1u)] = (uint16_t)tg[k];
-                                }
-                            } else {
-                                if (nout[k]) {
-                                    q2v[base & (G::D2 - 1u)] = x[k];
-                                    if constexpr (TAG) q2t[base & (G::D2 - 1u)] = (uint16_t)tg[k];
-                                }
-                            }
-                        }
-                        h1 += e;
-                        t2 += tot;
-                        st_fire[1] += 1;
-                        st_items[1] += e;
-                        st_full[1] += (e == EW);
-                    }
-                    if constexpr (!TAG) {
-                        while (sh1 < st1 && uni(sp1[sh1 & (G::SQ - 1u)]) == h1 && G::D2 - (t2 - h2) >= 1u &&
-                               st2 - sh2 < G::SQ) {
-                            const uint32_t j = uni(q1v[h1 & (G::D1 - 1u)]);
-                            if (t == 0) {
-                                q2v[t2 & (G::D2 - 1u)] = j;
-                                sp2[st2 & (G::SQ - 1u)] = t2;
-                            }
-                            ++t2;
-                            ++st2;
-                            ++h1;
-                            ++sh1;
-                            ++ej;
-                            st_sig[1] += 1;
-                        }
-                    }
-                    sync();
+                    if (e == EW) a_fire(BoolC<true>{}, e); else a_fire(BoolC<false>{}, e);
                     continue;
                 }
             }
-            // ---------------- F: the enumerating node
-            if (!fdone) {
-                uint32_t e, j_sig = 0;
-                bool ends_region = false;
-                if constexpr (TAG) {
-                    e = min(EW, vend - fpos);
-                } else {
-                    const uint32_t rend = uni(VT[fj + 1]);
-                    e = min(EW, rend - fpos);
-                    ends_region = (fpos + e == rend);
-                    j_sig = fj;
+            // ---------------- E
+            if constexpr (HAS_E) {
+                const uint32_t cap = (D2 - (t2 - h2)) / KE;   // inputs whose outputs surely fit
+                uint32_t e = 0;
+                bool sig = false, pending = false;
+                if constexpr (!TAG) {
+                    if (sh1 < st1) {
+                        pending = true;
+                        const uint32_t p = __builtin_amdgcn_readlane(sq1, sh1 & (SQ - 1u));
+                        if (p == h1) sig = true; else e = min(min(p - h1, EW), cap);
+                    }
                 }
-                const uint32_t space1 = G::D1 - (t1 - h1);
-                const bool sig_ok = TAG || !ends_region || (st1 - sh1 < G::SQ);
-                if (space1 >= e + (ends_region ? 1u : 0u) && sig_ok) {
-                    if (!f_stage(fpos, fj, e)) {
-                        failed = true;
-                        break;
+                if (sig) {
+                    if (st2 - sh2 < SQ) {   // forward the signal (sender rule: S2 has room)
+                        sq2 = t == (st2 & (SQ - 1u)) ? t2 : sq2;
+                        ++st2;
+                        ++sh1;
+                        ++ej;
+                        stat(ST_SIGNALS + 1, 1u);
+                        continue;
                     }
-                    uint32_t keep[V], item[V], aux[V], reg[V], off[V], tot;
-                    f_fire(fpos, fj, jlo, e, keep, item, aux, reg);
-                    ens_scan<W, V, false>(keep, off, tot, misc);
-#pragma unroll
-                    for (int k = 0; k < V; ++k) {
-                        if (keep[k]) {
-                            const uint32_t pos = (t1 + off[k]) & (G::D1 - 1u);
-                            q1v[pos] = item[k];
-                            if constexpr (KIND == RS_HASH_EXPAND) q1a[pos] = (uint8_t)aux[k];
-                            if constexpr (TAG) q1t[pos] = (uint16_t)reg[k];
-                        }
-                        if constexpr (TAG) {
-                            if ((uint32_t)k * W + t == e - 1u) misc[M_JLAST] = reg[k];
-                        }
+                } else {
+                    if (!pending) {
+                        const uint32_t n = t1 - h1;
+                        if (n >= EW || (fdone && n > 0)) e = min(min(n, EW), cap);
                     }
-                    t1 += tot;
-                    fpos += e;
                     if (e) {
-                        st_fire[0] += 1;
-                        st_items[0] += e;
-                        st_full[0] += (e == EW);
+                        if (e == EW) e_fire(BoolC<true>{}, e); else e_fire(BoolC<false>{}, e);
+                        continue;
                     }
-                    if constexpr (!TAG) {
-                        if (ends_region) {
-                            if (t == 0) {
-                                q1v[t1 & (G::D1 - 1u)] = j_sig;
-                                sp1[st1 & (G::SQ - 1u)] = t1;
-                            }
-                            ++t1;
-                            ++st1;
-                            ++fj;
-                            st_sig[0] += 1;
-                            fdone = (fj == nb);
-                        }
-                    }
-                    sync();
+                }
+            }
+            // ---------------- F
+            if (!fdone) {
+                const uint32_t lim = TAG ? vend : rend;
+                const uint32_t e = min(EW, lim - fpos);
+                const bool ends = !TAG && fpos + e == rend;
+                // room for every item (all might pass) and, at a region's end, for its signal
+                if (D1 - (t1 - h1) >= e && (!ends || st1 - sh1 < SQ)) {
+                    if (e == EW) f_node(BoolC<true>{}, e);
+                    else if (e) f_node(BoolC<false>{}, e);
                     if constexpr (TAG) {
-                        if (e) jlo = uni(misc[M_JLAST]);
                         fdone = (fpos == vend);
+                    } else if (ends) {
+                        sq1 = t == (st1 & (SQ - 1u)) ? t1 : sq1;
+                        ++st1;
+                        stat(ST_SIGNALS + 0, 1u);
+                        ++fj;
+                        fdone = (fj == nb);
+                        if (!fdone) {
+                            rend = uni(VT[fj + 1]);
+                            if constexpr (BYTES) {
+                                ls = uni(SX[fj]);
+                                lv = uni(VT[fj]);
+                            }
+                        }
                     }
                     continue;
                 }
             }
             // nothing fireable
-            if (fdone && h1 == t1 && h2 == t2) break;
+            if (fdone && h1 == t1 && h2 == t2 && sh1 == st1 && sh2 == st2) break;
             failed = true;   // cannot happen: some node is always fireable (Lemma 2)
             break;
         }
 
-        if constexpr (TAG) {
-            flush_tag();
-            sync();
-        }
-        ring_drain();
+        if constexpr (TAG) flush_wave(utag);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no staged copy outlives the claim
+        order();
         if (failed && t == 0) atomicOr(&a.ctl[CTL_ERROR], 1u);
 
         // ---- end(): one record per parent, written once
-        for (uint32_t i = t; i < nb; i += W) {
+        for (uint32_t i = t; i < nb; i += 64u) {
             const uint32_t p = p0 + i;
             if (a.agg_fields & RS_COUNT) sd.agg_count[p] = s_cnt[i];
             if (a.agg_fields & RS_SUM) sd.agg_sum[p] = s_sum[i];
             if (a.agg_fields & RS_MIN) sd.agg_min[p] = s_min[i];
             if (a.agg_fields & RS_MAX) sd.agg_max[p] = s_max[i];
         }
-        if (a.collect_stats && t == 0) {
-            for (int k = 0; k < 3; ++k) {
-                atomicAdd(&sd.stats[ST_FIRINGS + k], (unsigned long long)st_fire[k]);
-                atomicAdd(&sd.stats[ST_ITEMS + k], (unsigned long long)st_items[k]);
-                atomicAdd(&sd.stats[ST_FULL + k], (unsigned long long)st_full[k]);
-                atomicAdd(&sd.stats[ST_SIGNALS + k], (unsigned long long)st_sig[k]);
-            }
-        }
-        if (t == 0) misc[M_NEXT] = g_next;
-        sync();
+        if (a.collect_stats && t < ST_SIGNALS + 3 && stv) atomicAdd(&sd.stats[t], (unsigned long long)stv);
+        order();
         g = g1;
-        g1 = uni(misc[M_NEXT]);
+        g1 = g_next;
         cur = nxt;
     }
 
-    // last workgroup out returns the control block to zero for the next launch
+    // last wave out returns the control block to zero for the next launch
     if (t == 0) {
         __threadfence();
         const uint32_t d = atomicAdd(&a.ctl[CTL_DONE], 1u);
@@ -1088,16 +910,15 @@ __global__ void __launch_bounds__(W) rs_pipeline(LaunchArgs a) {
 
 using KernelFn = void (*)(LaunchArgs);
 
-// Ensemble width w = W * V: W lanes per workgroup, V items per lane per firing.  Every width
-// runs on single-wave processors: a wave's lanes share one scheduler with no barrier.
+// Ensemble width w = 64 * V: one wave, V items per lane per firing.
 template <int KIND, int STRAT>
 static KernelFn pick_width(uint32_t w) {
     switch (w) {
-        case 64: return rs_pipeline<KIND, STRAT, 64, 1>;
-        case 128: return rs_pipeline<KIND, STRAT, 64, 2>;
-        case 256: return rs_pipeline<KIND, STRAT, 64, 4>;
-        case 512: return rs_pipeline<KIND, STRAT, 64, 8>;
-        case 1024: return rs_pipeline<KIND, STRAT, 64, 16>;
+        case 64: return rs_pipeline<KIND, STRAT, 1>;
+        case 128: return rs_pipeline<KIND, STRAT, 2>;
+        case 256: return rs_pipeline<KIND, STRAT, 4>;
+        case 512: return rs_pipeline<KIND, STRAT, 8>;
+        case 1024: return rs_pipeline<KIND, STRAT, 16>;
         default: return nullptr;
     }
 }
@@ -1118,6 +939,8 @@ static KernelFn pick(uint32_t kind, uint32_t s, uint32_t w) {
 }
 
 uint32_t lanes_of(uint32_t ensemble_width) { return ensemble_width ? 64u : 0u; }
+
+uint32_t dyn_lds_bytes(uint32_t kind, uint32_t bmax) { return dyn_layout(kind, bmax).bytes; }
 
 // ---------------------------------------------------------------- HBM probe
 
@@ -1144,15 +967,17 @@ int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const Laun
                     void *stream) {
     KernelFn k = pick(kind, strategy, width);
     if (!k) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), dyn_lds_bytes(kind, a.bmax), (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
-int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width) {
+int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t bmax) {
     KernelFn k = pick(kind, strategy, width);
     if (!k) return 0;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)lanes_of(width), 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)lanes_of(width), dyn_lds_bytes(kind, bmax)) !=
+        hipSuccess)
+        return 0;
     return n;
 }
 

@@ -133,7 +133,6 @@ struct rs_pipeline {
     hipStream_t own[2] = {nullptr, nullptr};
     hipStream_t user_stream = nullptr;
     bool one_lane = false;         // every batch on the first lane (the per-stream baseline)
-    DevBuf dummy;
     uint32_t width = 0, strategy = 0;
     bool configured = false;
     uint64_t next_id = 1, next_batch = 1;
@@ -243,6 +242,7 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     b->lane = lane_of(p, batch_id);
     std::vector<rs::StreamDev> h(sel.size());
     uint64_t claims = 0;
+    uint32_t bmax = 1;
     for (size_t i = 0; i < sel.size(); ++i) {
         Stream *s = sel[i];
         uint32_t P = s->n_parents;
@@ -275,6 +275,7 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
         e.n_parents = P;
         e.n_elements = s->n_elements;
         e.parents_per_claim = s->B;
+        bmax = std::max(bmax, std::min(s->B, P));
         e.n_claims = s->n_claims;
         e.claim_begin = (uint32_t)claims;
         claims += s->n_claims;
@@ -290,20 +291,20 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     HIP_OR(hipStreamSynchronize(b->lane), RS_EDEVICE);   // h is a local array
     HIP_OR(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), RS_EDEVICE);
     b->total_claims = (uint32_t)claims;
-    const int per_cu = rs::blocks_per_cu(p->d.kind, p->strategy, p->width);
+    const int per_cu = rs::blocks_per_cu(p->d.kind, p->strategy, p->width, bmax);
     if (per_cu <= 0) return fail(RS_EDEVICE, "kernel does not fit on a compute unit");
     // every workgroup holds two claims at a time (the next one's region table is prefetched)
     b->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((claims + 1) / 2, (uint64_t)per_cu * p->n_cu));
     rs::LaunchArgs &a = b->args;
     a.streams = (const rs::StreamDev *)b->table.p;
     a.ctl = (uint32_t *)b->ctl.p;
-    a.dummy = p->dummy.p;
     a.n_streams = (uint32_t)sel.size();
     a.total_claims = b->total_claims;
     std::memcpy(a.param, p->d.param, sizeof a.param);
     a.agg_fields = p->d.agg_fields;
     a.collect_stats = (!probe && (p->d.flags & RS_COLLECT_STATS)) ? 1u : 0u;
     a.emit_outputs = (!probe && p->d.emit_outputs) ? 1u : 0u;
+    a.bmax = bmax;
     out = std::move(b);
     return RS_OK;
 }
@@ -484,9 +485,6 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     HIP_OR(hipGetDeviceProperties(&prop, p->device), RS_EDEVICE);
     p->n_cu = prop.multiProcessorCount;
     for (auto &h : p->own) HIP_OR(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), RS_EDEVICE);
-    int rc = p->dummy.alloc(256);
-    if (rc) return rc;
-    HIP_OR(hipMemset(p->dummy.p, 0, 256), RS_EDEVICE);
     p->width = d->ensemble_width;
     p->strategy = d->strategy == RS_AUTO ? RS_TAG : d->strategy;
     p->configured = d->ensemble_width != 0 && d->strategy != RS_AUTO;
