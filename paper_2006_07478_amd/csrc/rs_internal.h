@@ -4,15 +4,16 @@
 
 namespace rs {
 
-// Device control block of a pipeline (one per pipeline, zero-initialised once).
-// The persistent kernel returns every counter to zero before it exits, so a launch
-// can be replayed (HIP graph) without any reset node.
+// Device control block of a batch (zero-initialised once).  A one-wave reset kernel runs
+// before every launch of the pipeline kernel on the same stream: it zeroes the claim
+// counters and advances the epoch, so a launch can be replayed (HIP graph) as is.
 enum Ctl : uint32_t {
-    CTL_CLAIM = 0,     // next global claim index
-    CTL_DONE = 1,      // workgroups that have exited
-    CTL_ERROR = 2,     // watchdog / protocol error flag (sticky until read)
-    CTL_EPOCH = 3,     // launches completed (look-back state tags)
-    CTL_WORDS = 64
+    CTL_ERROR = 2,          // watchdog / protocol error flag (sticky until read)
+    CTL_EPOCH = 3,          // launch epoch (look-back state tags)
+    CTL_NPART = 8,          // claim partitions, at most (one per XCD)
+    CTL_PART = 64,          // claim counter of partition q at CTL_PART + q * CTL_PART_STRIDE
+    CTL_PART_STRIDE = 32,   // one 128-byte line per counter
+    CTL_WORDS = CTL_PART + CTL_NPART * CTL_PART_STRIDE
 };
 
 // Statistics slots per stream (u64 each).
@@ -57,7 +58,8 @@ struct LaunchArgs {
     uint32_t collect_stats;
     uint32_t emit_outputs;
     uint32_t bmax;                 // most parents in any claim of the launch (sizes the per-claim LDS)
-    uint32_t pad[3];
+    uint32_t n_parts;              // claim partitions: CTL_NPART, or 1 when claims must start in order
+    uint32_t pad[2];
 };
 
 // Kernel entry points (defined in rs_kernels.hip).

@@ -60,25 +60,101 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+template <class T>
+__device__ __forceinline__ T *uni_ptr(T *p) {
+    const uint64_t v = (uint64_t)p;
+    return (T *)(((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v));
+}
+
 // Lanes of one wave see each other's LDS writes in issue order; this only keeps the
 // compiler from moving memory accesses across the point.
 __device__ __forceinline__ void order() { asm volatile("" ::: "memory"); }
 
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Buffer resource over [base, base + bytes): loads outside the range return zero.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+// LDS byte address of a __shared__ object
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
 }
 
-// Rounds K.. of a staged ensemble copy: round k moves words k*64 + lane from the buffer to
-// LDS; the instruction's immediate offset advances both the buffer and the LDS address.
-template <int K, int V>
-__device__ __forceinline__ void stage_rounds(__amdgpu_buffer_rsrc_t r, lds_void_t *dst, uint32_t voff) {
-    if constexpr (K < V) {
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, voff, 0, K * 256, 0);
-        stage_rounds<K + 1, V>(r, dst, voff);
+// Buffer resource over [base, base + bytes): loads outside the range return zero.
+// Base and size are made wave-uniform, so the resource lives in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(uni_ptr(const_cast<void *>(base)), (short)0, (int)uni(bytes),
+                                             0x00020000);
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Buffer resource words over [base, base + bytes), wave-uniform: loads outside the range
+// return zero.
+__device__ __forceinline__ u32x4 rsrc_words(const void *base, uint32_t bytes) {
+    const uint64_t b = (uint64_t)uni_ptr(base);
+    u32x4 r;
+    r.x = (uint32_t)b;
+    r.y = (uint32_t)(b >> 32) & 0xFFFFu;
+    r.z = uni(bytes);
+    r.w = 0x00020000u;
+    return r;
+}
+
+#define RS_LDSCOPY(off) "buffer_load_dword %[v], %[r], 0 offen offset:" #off " lds\n\t"
+#define RS_LDSCOPY4(a, b, c, d) RS_LDSCOPY(a) RS_LDSCOPY(b) RS_LDSCOPY(c) RS_LDSCOPY(d)
+
+// Copies V rounds of 64 words from the buffer to LDS at lds_base: round k moves word
+// k*64 + lane (the immediate offset advances both addresses).  The copy is written as asm so
+// that the compiler neither orders other LDS accesses behind it nor waits for it: its
+// completion is awaited explicitly (vmcnt) before the words are read.  m0 holds the LDS base
+// and is restored afterwards.
+template <int V>
+__device__ __forceinline__ void lds_copy(u32x4 r, uint32_t lds_base, uint32_t voff) {
+    uint32_t save;
+    if constexpr (V == 1) {
+        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY(0) "s_mov_b32 m0, %[s]"
+                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+    } else if constexpr (V == 2) {
+        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY(0) RS_LDSCOPY(256)
+                     "s_mov_b32 m0, %[s]"
+                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+    } else if constexpr (V == 4) {
+        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY4(0, 256, 512, 768)
+                     "s_mov_b32 m0, %[s]"
+                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+    } else if constexpr (V == 8) {
+        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY4(0, 256, 512, 768)
+                     RS_LDSCOPY4(1024, 1280, 1536, 1792) "s_mov_b32 m0, %[s]"
+                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+    } else {
+        static_assert(V == 16, "ensemble rounds");
+        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY4(0, 256, 512, 768)
+                     RS_LDSCOPY4(1024, 1280, 1536, 1792) RS_LDSCOPY4(2048, 2304, 2560, 2816)
+                     RS_LDSCOPY4(3072, 3328, 3584, 3840) "s_mov_b32 m0, %[s]"
+                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
     }
+}
+
+// Slot of queue position base + i in a ring of D slots, where base < D and i < D: a mask for
+// a power of two, else one conditional subtraction written as an unsigned minimum.
+template <uint32_t D>
+__device__ __forceinline__ uint32_t qslot(uint32_t base, uint32_t i) {
+    if constexpr ((D & (D - 1u)) == 0u) {
+        return (base + i) & (D - 1u);
+    } else {
+        const uint32_t p = base + i;
+        return min(p, p - D);
+    }
+}
+
+// a where the lane's bit of mask is set, else b (one v_cndmask, never a branch)
+__device__ __forceinline__ uint32_t pick(uint64_t mask, uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+    return r;
+}
+
+// Wait until at most N vector-memory operations of this wave are outstanding; also a
+// compiler barrier, so no memory access moves across it.
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
 template <bool B>
@@ -149,9 +225,10 @@ template <int V, bool HAS_E, uint32_t KE>
 struct Geo {
     static constexpr uint32_t EW = 64u * V;   // ensemble width: items one firing consumes
     static constexpr uint32_t D1 = 2u * EW;   // data slots in front of the second node
-    // in front of the third node: room for one full ensemble's worst-case output on top
-    // of an almost full ensemble, so the second node always fires full ensembles
-    static constexpr uint32_t D2 = HAS_E ? (KE == 3u ? 4u * EW : 2u * EW) : 1u;
+    // in front of the third node: the third node drains it below one ensemble before the
+    // second fires, so room for one full ensemble's worst-case output (KE per input) on top
+    // lets the second node always fire full ensembles
+    static constexpr uint32_t D2 = HAS_E ? (KE == 3u ? 3u * EW : 2u * EW) : 1u;
     static constexpr uint32_t SQ = 64u;       // signal queue capacity (the finite S of §3.1)
     static constexpr uint32_t R = 4u;         // region-table rows per lane (256 entries)
 };
@@ -178,6 +255,35 @@ __host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t bmax) {
     d.mx = o;
     o += 4u * bmax;
     d.bytes = (o + 15u) & ~15u;
+    return d;
+}
+
+// A stream-table entry held in scalar registers: every field is read once and made
+// wave-uniform, so buffer resources and loop bounds built from it need no per-lane handling.
+struct SDesc {
+    const uint8_t *elements;
+    const uint32_t *offsets, *lengths, *pparam;
+    uint32_t *agg_count, *agg_min, *agg_max, *out_items;
+    unsigned long long *agg_sum, *lookback, *stats;
+    uint32_t n_parents, n_elements, B, claim_begin;
+};
+__device__ __forceinline__ SDesc load_sdesc(const StreamDev &s) {
+    SDesc d;
+    d.elements = uni_ptr((const uint8_t *)s.elements);
+    d.offsets = uni_ptr(s.offsets);
+    d.lengths = uni_ptr(s.lengths);
+    d.pparam = uni_ptr(s.pparam);
+    d.agg_count = uni_ptr(s.agg_count);
+    d.agg_sum = uni_ptr(s.agg_sum);
+    d.agg_min = uni_ptr(s.agg_min);
+    d.agg_max = uni_ptr(s.agg_max);
+    d.out_items = uni_ptr(s.out_items);
+    d.lookback = uni_ptr(s.lookback);
+    d.stats = uni_ptr(s.stats);
+    d.n_parents = uni(s.n_parents);
+    d.n_elements = uni(s.n_elements);
+    d.B = uni(s.parents_per_claim);
+    d.claim_begin = uni(s.claim_begin);
     return d;
 }
 
@@ -208,7 +314,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     __shared__ uint8_t q1t[TAG ? D1 + 64 : 1];
     __shared__ uint32_t q2v[HAS_E ? D2 + 64 : 1];
     __shared__ uint8_t q2t[(HAS_E && TAG) ? D2 + 64 : 1];
-    __shared__ uint32_t fsl[BYTES ? 1 : EW];   // staging slot: the enumerating node's next ensemble
+    __shared__ uint32_t fsl[BYTES ? 1 : 2 * EW];   // two staging slots for the enumerating node
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
 
     const Dyn lay = dyn_layout(KIND, a.bmax);
@@ -227,8 +333,8 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     const uint32_t modr = a.param[1];
     const bool mod_pow2 = (modm & (modm - 1u)) == 0u;
 
-    // launches completed so far, as a 24-bit tag in [1, 2^24 - 1] for the look-back words
-    // (the control block only changes after every wave of a launch has finished)
+    // this launch's epoch (set by the reset kernel before it), as a 24-bit tag in
+    // [1, 2^24 - 1] for the look-back words
     const uint32_t epoch_tag =
         uni(__hip_atomic_load(&a.ctl[CTL_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) % 0xFFFFFFu + 1u;
 
@@ -239,15 +345,25 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             const uint32_t mid = (lo + hi) >> 1;
             if (a.streams[mid].claim_begin <= gg) lo = mid; else hi = mid;
         }
-        return lo;
+        return uni(lo);
+    };
+    // the stream-table entry last read (consecutive claims usually share a stream)
+    SDesc sdc;
+    uint32_t sdc_idx = 0xFFFFFFFFu;
+    auto ensure_sd = [&](uint32_t si) {
+        if (si != sdc_idx) {
+            sdc = load_sdesc(a.streams[si]);
+            sdc_idx = si;
+        }
     };
     // this lane's share of the region table of claim gg (loads only; consumed a claim later)
     auto load_claim = [&](uint32_t gg, ClaimRegs<R> &r) {
 #pragma unroll
         for (uint32_t q = 0; q < R; ++q) r.off[q] = r.len[q] = r.ctx[q] = 0;
         if (gg >= a.total_claims) return;
-        const StreamDev &sd = a.streams[stream_of(gg)];
-        const uint32_t B = sd.parents_per_claim;
+        ensure_sd(stream_of(gg));
+        const SDesc &sd = sdc;
+        const uint32_t B = sd.B;
         const uint32_t p0 = (gg - sd.claim_begin) * B;
         const uint32_t nb = min(B, sd.n_parents - p0);
 #pragma unroll
@@ -266,10 +382,49 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
         }
     };
+    // Claims.  The launch's claims are split into n_parts contiguous partitions, one per XCD
+    // (workgroups are dispatched round-robin over the XCDs), each with its own counter in its
+    // own cache line, so claim traffic spreads over independent atomics.  A wave first takes
+    // about three quarters of its home partition's claims by its index (claims widx,
+    // widx + Wp, widx + 2 Wp, ... for the partition's Wp waves; no atomic at all), then claims
+    // from its home counter, and when that partition is used up, from the other partitions'
+    // counters; a plain read skips a used-up counter without an atomic.
+    const uint32_t n_claims = a.total_claims, np = a.n_parts, n_waves = gridDim.x;
+    const uint32_t home = blockIdx.x % np, widx = blockIdx.x / np;
+    auto p_begin = [&](uint32_t q) -> uint32_t { return (uint32_t)(((uint64_t)n_claims * q) / np); };
+    auto p_waves = [&](uint32_t q) -> uint32_t { return n_waves > q ? (n_waves - 1u - q) / np + 1u : 0u; };
+    // claims each wave of partition q takes by index (at least two: the two claims in hand)
+    auto p_static = [&](uint32_t q) -> uint32_t {
+        const uint32_t wq = p_waves(q), size = p_begin(q + 1u) - p_begin(q);
+        return wq ? max(2u, size / 4u * 3u / wq) : 0u;
+    };
+    const uint32_t home_static = p_static(home), home_waves = p_waves(home);
+    uint32_t n_static = 0, tried = 0;
     auto take_claim = [&]() -> uint32_t {
-        uint32_t c = 0;
-        if (t == 0) c = atomicAdd(&a.ctl[CTL_CLAIM], 1u);
-        return uni(c);
+        while (n_static < home_static) {
+            const uint32_t c = p_begin(home) + widx + n_static * home_waves;
+            ++n_static;
+            if (c < p_begin(home + 1u)) return c;
+            n_static = home_static;
+        }
+        while (tried < np) {
+            const uint32_t q = (home + tried) % np;
+            const uint32_t first = p_begin(q) + p_static(q) * p_waves(q), end = p_begin(q + 1u);
+            if (first < end) {
+                uint32_t got = 0xFFFFFFFFu;
+                if (t == 0) {
+                    uint32_t *ctr = &a.ctl[CTL_PART + q * CTL_PART_STRIDE];
+                    if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < end - first) {
+                        const uint32_t k = atomicAdd(ctr, 1u);
+                        if (k < end - first) got = first + k;
+                    }
+                }
+                got = uni(got);
+                if (got != 0xFFFFFFFFu) return got;
+            }
+            ++tried;
+        }
+        return n_claims;   // nothing left
     };
 
     // claims are taken two ahead: g is worked on, g1 is next (its region table in registers)
@@ -283,9 +438,10 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         ClaimRegs<R> nxt;
         load_claim(g1, nxt);                    // consumed at the next claim
 
-        const StreamDev &sd = a.streams[stream_of(g)];
-        const uint8_t *const elems = (const uint8_t *)sd.elements;
-        const uint32_t B = sd.parents_per_claim;
+        ensure_sd(stream_of(g));
+        const SDesc &sd = sdc;
+        const uint8_t *const elems = sd.elements;
+        const uint32_t B = sd.B;
         const uint32_t cidx = g - sd.claim_begin;
         const uint32_t p0 = cidx * B;
         const uint32_t nb = uni(min(B, sd.n_parents - p0));
@@ -370,17 +526,22 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // text: the whole byte array (addresses fit in 32 bits); word loads near its end fall
         // back to bytes, so no load depends on the range check for its value
         const __amdgpu_buffer_rsrc_t rtext = rsrc(elems, BYTES ? sd.n_elements : 0u);
-        // u32 elements: the ensemble at position pos is copied to the staging slot by direct
-        // buffer->LDS loads (item k*64 + lane to word k*64 + lane; positions past vend read as
-        // zero).  The copy is issued as soon as the slot's previous contents have been taken, so
-        // it overlaps the downstream firings; its completion is awaited explicitly.
-        uint32_t staged = 0xFFFFFFFFu;   // position whose ensemble the slot holds or is receiving
-        auto stage = [&](uint32_t pos) {
+        // u32 elements: the ensemble starting at position pos is copied to a staging slot by
+        // direct buffer->LDS loads (item k*64 + lane to word k*64 + lane; positions past vend
+        // read as zero).  Two slots alternate: a firing requests the ensemble of the firing after
+        // next into the slot it has just read, so a copy has two firings' time to land even when
+        // the enumerating node fires twice in a row.  Completion is awaited explicitly: a slot
+        // whose copy is older than the other slot's needs all but the newest V loads done.
+        uint32_t spos0 = 0xFFFFFFFFu, spos1 = 0xFFFFFFFFu;   // position each slot holds or receives
+        uint32_t last = 0;                                    // slot whose copy was issued last
+        auto stage = [&](uint32_t pos, uint32_t slot) {
             if constexpr (!BYTES) {
+                if (slot) spos1 = 0xFFFFFFFFu; else spos0 = 0xFFFFFFFFu;
                 if (pos < vend) {
-                    const __amdgpu_buffer_rsrc_t r = rsrc(elems + (size_t)pos * 4u, min(EW, vend - pos) * 4u);
-                    stage_rounds<0, V>(r, (lds_void_t *)fsl, t * 4u);
-                    staged = pos;
+                    lds_copy<V>(rsrc_words(elems + (size_t)pos * 4u, min(EW, vend - pos) * 4u),
+                                uni(lds_addr(fsl) + slot * EW * 4u), t * 4u);
+                    if (slot) spos1 = pos; else spos0 = pos;
+                    last = slot;
                 }
             }
         };
@@ -519,12 +680,18 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 
         // ---- node state (all uniform)
         uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;            // data queue heads and tails
+        uint32_t h2w = 0, t2w = 0;                          // their slots in the second queue
         uint32_t sh1 = 0, st1 = 0, sh2 = 0, st2 = 0;        // signal queue heads and tails
         uint32_t sq1 = 0, sq2 = 0;                          // signal queues (entry n in lane n mod 64)
         // enumerating node: signal strategy walks region fj at position fpos;
         // tag strategy walks ensembles of EW consecutive positions from fpos.
         uint32_t fj = 0, fpos = vbeg, jlo = 0;
         uint32_t rend = 0, ls = 0, lv = 0;                  // current region's end, line address, line position
+        // tag strategy: start of region jlo + 1 (every position below it lies in region jlo or before)
+        uint32_t jnext = 0xFFFFFFFFu;
+        if constexpr (TAG) {
+            if (nb > 1u) jnext = uni((BYTES ? SX : VT)[1]);
+        }
         if constexpr (!TAG) {
             if (nb) {
                 rend = uni(VT[1]);
@@ -539,14 +706,17 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         uint32_t utag = 0;                    // tag strategy: region every lane's accumulator belongs to
         // lane n counts statistic n of this claim: firings, items, full firings and signals per node
         uint32_t stv = 0;
-        auto stat = [&](uint32_t n, uint32_t v) { stv += (t == n) ? v : 0u; };
+        const bool collect = a.collect_stats != 0u;
+        auto stat = [&](uint32_t n, uint32_t v) {
+            if (collect) stv += (t == n) ? v : 0u;
+        };
         // every scheduler iteration fires a node; a claim needs at most a few firings per
         // element and per region, so this bound only trips on a scheduling error
         const uint32_t iter_cap =
             (uint32_t)min(8ull * ((unsigned long long)(vend - vbeg) + nb) + 64ull, 0xFFFFFFFFull);
         uint32_t iters = 0;
 
-        stage(fpos);
+        stage(fpos, 0);
 
         // per-lane flush of the accumulator into region slot j (LDS atomics)
         auto flush_lane = [&](uint32_t j) {
@@ -573,20 +743,24 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // ---------------- A: the aggregating node, one firing of e items from its queue head
         auto a_fire = [&](auto full, uint32_t e) {
             constexpr bool FULL = decltype(full)::value;
-            const uint32_t hq = HAS_E ? h2 : h1;
+            const uint32_t hw = HAS_E ? h2w : (h1 & (D1 - 1u));   // head slot
             const uint32_t *qv = HAS_E ? q2v : q1v;
             const uint8_t *qt = HAS_E ? q2t : q1t;
             uint32_t y[V], tg[V];
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const uint32_t pos = (hq + (uint32_t)k * 64u + t) & (DA - 1u);
+                const uint32_t pos = qslot<DA>(hw, (uint32_t)k * 64u + t);
                 y[k] = qv[pos];
                 if constexpr (TAG) tg[k] = qt[pos]; else tg[k] = 0u;
             }
             uint32_t tf = 0, tl = 0;
             if constexpr (TAG) {
-                tf = uni(qt[hq & (DA - 1u)]);
-                tl = uni(qt[(hq + e - 1u) & (DA - 1u)]);
+                // tags of the ensemble's first and last items, from the values just read
+                tf = uni(tg[0]);
+                const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
+#pragma unroll
+                for (int k = 0; k < V; ++k)
+                    if ((uint32_t)k == kl) tl = __builtin_amdgcn_readlane(tg[k], ll);
             }
 #pragma unroll
             for (int k = 0; k < V; ++k) {
@@ -626,7 +800,12 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 flush_lane(lt);
                 utag = tl;
             }
-            if constexpr (HAS_E) h2 += e; else h1 += e;
+            if constexpr (HAS_E) {
+                h2 += e;
+                h2w = qslot<D2>(h2w, e);
+            } else {
+                h1 += e;
+            }
             a_items += e;
             out_rank += e;
             stat(ST_FIRINGS + 2, 1u);
@@ -676,40 +855,49 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     x[k] = p - x[k];
                 }
             }
-            uint32_t run = 0;
+            // The firing takes the longest prefix of the ensemble whose outputs fit the free
+            // slots (the scheduler guarantees room for the first item's worst case); offsets are
+            // exclusive prefixes in ensemble order, so the items that fit form a prefix.
+            const uint32_t room = D2 - (t2 - h2);
+            uint32_t run = 0, taken = 0, made = 0;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
                 const bool act = FULL || (uint32_t)k * 64u + t < e;
                 const uint32_t nout = act ? c[k] : 0u;
                 const uint64_t b0 = __ballot(nout & 1u);
                 uint32_t within = rank_below(b0), pc = (uint32_t)__popcll(b0);
+                uint64_t b1 = 0;
                 if constexpr (KE == 3u) {
-                    const uint64_t b1 = __ballot(nout & 2u);
+                    b1 = __ballot(nout & 2u);
                     within += 2u * rank_below(b1);
                     pc += 2u * (uint32_t)__popcll(b1);
                 }
-                const uint32_t base = t2 + run + within;
+                const uint32_t off = run + within;
+                const uint64_t fits = __ballot(act && off + nout <= room);
+                taken += (uint32_t)__popcll(fits);
+                made += (uint32_t)__popcll(b0 & fits) + 2u * (uint32_t)__popcll(b1 & fits);
 #pragma unroll
                 for (uint32_t ch = 0; ch < KE; ++ch) {
-                    const uint32_t pos = ch < nout ? ((base + ch) & (D2 - 1u)) : D2 + t;
+                    const uint32_t pos = pick(__ballot(ch < nout) & fits, qslot<D2>(t2w, off + ch), D2 + t);
                     // child ch of x leaves as its pre-image x ^ K(ch+1) (hash kind); a word as its length
                     q2v[pos] = KIND == RS_HASH_EXPAND ? x[k] ^ salt_key(ch + 1u) : x[k];
                     if constexpr (TAG) q2t[pos] = (uint8_t)tg[k];
                 }
                 run += pc;
             }
-            h1 += e;
-            t2 += run;
+            h1 += taken;
+            t2 += made;
+            t2w = qslot<D2>(t2w, made);
             stat(ST_FIRINGS + 1, 1u);
-            stat(ST_ITEMS + 1, e);
-            if constexpr (FULL) stat(ST_FULL + 1, 1u);
+            stat(ST_ITEMS + 1, taken);
+            stat(ST_FULL + 1, taken == EW ? 1u : 0u);
         };
 
         // ---------------- F: the enumerating node, one firing of e items from fpos
         auto f_node = [&](auto full, uint32_t e) {
             constexpr bool FULL = decltype(full)::value;
             bool one = true;
-            if constexpr (TAG) one = jlo + 1u >= nb || uni((BYTES ? SX : VT)[jlo + 1u]) > fpos + e - 1u;
+            if constexpr (TAG) one = jnext > fpos + e - 1u;
             uint32_t reg[V], x[V];
             if constexpr (TAG) {
                 f_regions(full, fpos, e, jlo, one, reg);
@@ -717,11 +905,21 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) reg[k] = fj;
             }
+            uint32_t slot = 0;
             if constexpr (!BYTES) {
-                if (staged != fpos) stage(fpos);
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the staged copy has landed
+                if (spos0 == fpos) {
+                    slot = 0;
+                } else if (spos1 == fpos) {
+                    slot = 1;
+                } else {
+                    slot = last ^ 1u;
+                    stage(fpos, slot);
+                }
+                // the slot's copy has landed: if the other slot's copy is newer, only its V
+                // loads may still be outstanding
+                if (last != slot) wait_vmem<V>(); else wait_vmem<0>();
 #pragma unroll
-                for (int k = 0; k < V; ++k) x[k] = fsl[k * 64 + t];
+                for (int k = 0; k < V; ++k) x[k] = fsl[slot * EW + k * 64 + t];
             } else {
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = 0;
@@ -736,7 +934,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint64_t b = __ballot(keep);
                 const uint32_t within = rank_below(b), pc = (uint32_t)__popcll(b);
                 // dropped lanes write spill slots on the banks the kept ones leave free
-                const uint32_t pos = keep ? ((t1 + run + within) & (D1 - 1u)) : D1 + ((t1 + run + pc + t - within) & 63u);
+                const uint32_t pos = pick(b, (t1 + run + within) & (D1 - 1u), D1 + ((t1 + run + pc + t - within) & 63u));
                 q1v[pos] = item;
                 if constexpr (KIND == RS_HASH_EXPAND) q1a[pos] = (uint8_t)aux;
                 if constexpr (TAG) q1t[pos] = (uint8_t)reg[k];
@@ -748,9 +946,26 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                     for (int k = 0; k < V; ++k)
                         if ((uint32_t)k == kl) jlo = __builtin_amdgcn_readlane(reg[k], ll);
+                    jnext = jlo + 1u < nb ? uni((BYTES ? SX : VT)[jlo + 1u]) : 0xFFFFFFFFu;
                 }
             }
-            stage(fpos + e);   // the slot's contents are in registers: load the next ensemble
+            if constexpr (!BYTES) {
+                // the next firing starts at p1 (its copy is in the other slot, or requested now);
+                // the one after starts at p2 and goes to the slot just read
+                const uint32_t p1 = fpos + e;
+                uint32_t p2 = p1;
+                if (p1 < vend) {
+                    uint32_t r1 = vend;   // end of the ensemble that starts at p1
+                    if constexpr (!TAG) {
+                        uint32_t j = fj;
+                        r1 = rend;
+                        while (r1 <= p1 && j + 1u < nb) r1 = uni(VT[++j + 1u]);
+                    }
+                    p2 = p1 + min(EW, r1 - p1);
+                }
+                if ((slot ? spos0 : spos1) != p1) stage(p1, slot ^ 1u);
+                stage(p2, slot);
+            }
             t1 += run;
             fpos += e;
             stat(ST_FIRINGS + 0, 1u);
@@ -810,14 +1025,16 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             // ---------------- E
             if constexpr (HAS_E) {
-                const uint32_t cap = (D2 - (t2 - h2)) / KE;   // inputs whose outputs surely fit
+                // E may fire when the first item's worst-case output fits; the firing itself
+                // keeps only the prefix whose actual outputs fit
+                const bool room = D2 - (t2 - h2) >= KE;
                 uint32_t e = 0;
                 bool sig = false, pending = false;
                 if constexpr (!TAG) {
                     if (sh1 < st1) {
                         pending = true;
                         const uint32_t p = __builtin_amdgcn_readlane(sq1, sh1 & (SQ - 1u));
-                        if (p == h1) sig = true; else e = min(min(p - h1, EW), cap);
+                        if (p == h1) sig = true; else if (room) e = min(p - h1, EW);
                     }
                 }
                 if (sig) {
@@ -832,7 +1049,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 } else {
                     if (!pending) {
                         const uint32_t n = t1 - h1;
-                        if (n >= EW || (fdone && n > 0)) e = min(min(n, EW), cap);
+                        if (room && (n >= EW || (fdone && n > 0))) e = min(n, EW);
                     }
                     if (e) {
                         if (e == EW) e_fire(BoolC<true>{}, e); else e_fire(BoolC<false>{}, e);
@@ -893,17 +1110,6 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         g1 = g_next;
         cur = nxt;
     }
-
-    // last wave out returns the control block to zero for the next launch
-    if (t == 0) {
-        __threadfence();
-        const uint32_t d = atomicAdd(&a.ctl[CTL_DONE], 1u);
-        if (d == gridDim.x - 1u) {
-            atomicExch(&a.ctl[CTL_CLAIM], 0u);
-            atomicExch(&a.ctl[CTL_DONE], 0u);
-            atomicAdd(&a.ctl[CTL_EPOCH], 1u);
-        }
-    }
 }
 
 // ---------------------------------------------------------------- launch table
@@ -963,10 +1169,20 @@ bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width) {
     return pick(kind, strategy, width) != nullptr;
 }
 
+// Prepares the control block for the launch that follows it on the same stream: claim
+// counters to zero, and a new epoch for the look-back words.  A separate kernel (not a
+// memset) so that a captured graph replays it correctly.
+__global__ void __launch_bounds__(64) rs_reset(uint32_t *ctl) {
+    const uint32_t t = threadIdx.x;
+    if (t < CTL_NPART) ctl[CTL_PART + t * CTL_PART_STRIDE] = 0u;
+    if (t == 0) ctl[CTL_EPOCH] += 1u;
+}
+
 int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a, uint32_t grid,
                     void *stream) {
     KernelFn k = pick(kind, strategy, width);
     if (!k) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(rs_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, a.ctl);
     hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), dyn_lds_bytes(kind, a.bmax), (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }

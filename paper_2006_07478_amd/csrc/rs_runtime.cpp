@@ -305,6 +305,8 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     a.collect_stats = (!probe && (p->d.flags & RS_COLLECT_STATS)) ? 1u : 0u;
     a.emit_outputs = (!probe && p->d.emit_outputs) ? 1u : 0u;
     a.bmax = bmax;
+    // the ordered output stream's look-back needs claims started in index order
+    a.n_parts = a.emit_outputs ? 1u : rs::CTL_NPART;
     out = std::move(b);
     return RS_OK;
 }
