@@ -49,7 +49,8 @@ enum rs_status {
     RS_ENOTFOUND = -7   /* unknown stream id */
 };
 
-/* Boundary transport.  RS_SIGNAL: in-band boundary signals with credit (§3);
+/* Boundary transport.  RS_SIGNAL: end-of-region signals on a finite signal queue beside each
+ * data queue, delivered precisely with credit (§3.1-§3.3);
  * RS_TAG: a region tag on every item (§5); RS_AUTO: the autotuner chooses. */
 enum rs_strategy { RS_TAG = 0, RS_SIGNAL = 1, RS_AUTO = 2 };
 
@@ -95,7 +96,8 @@ typedef struct rs_pipeline rs_pipeline;   /* opaque, library-owned */
  *   strategy        rs_strategy
  *   agg_fields      OR of rs_aggf: the fields the pipeline stores (others are not written)
  *   ensemble_width  0 = autotune, else 64, 128, 256, 512 or 1024: the SIMD width w, the largest
- *                   ensemble one firing of a node consumes (§2.2; one workgroup of w lanes)
+ *                   ensemble one firing of a node consumes (§2.2; one wave64 processes w/64
+ *                   items per lane per firing)
  *   queue_depth     0 = default; else the capacity in slots of the queue in front of every
  *                   stage, a power of two >= 2*ensemble_width (the stage maxima need room for
  *                   k*w outputs plus signal slots, §3.2 fireability)
@@ -184,7 +186,8 @@ int pipeline_set_stream(rs_pipeline *p, void *hip_stream);
 int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id);
 
 /* Process every pushed stream that has not run yet: admitted streams (by budget) go into one
- * persistent launch in which workgroups claim parent batches with device atomics (§2.2);
+ * persistent launch in which one-wave processors take parent batches from per-XCD
+ * partitions of the launch's claims, by index or from a partition counter (§2.2);
  * streams that do not fit wait for the next run().  RS_RUN_SYNC waits for completion.
  * Errors: RS_EDEVICE (HIP error or watchdog), RS_ESTATE (nothing to run is not an error: RS_OK). */
 int run(rs_pipeline *p, uint32_t flags);
