@@ -10,7 +10,7 @@ namespace rs {
 enum Ctl : uint32_t {
     CTL_ERROR = 2,          // watchdog / protocol error flag (sticky until read)
     CTL_EPOCH = 3,          // launch epoch (look-back state tags)
-    CTL_NPART = 8,          // claim partitions, at most (one per XCD)
+    CTL_NPART = 64,         // claim partitions (8 per XCD); a launch uses 64, or 1 (the kernel relies on this)
     CTL_PART = 64,          // claim counter of partition q at CTL_PART + q * CTL_PART_STRIDE
     CTL_PART_STRIDE = 32,   // one 128-byte line per counter
     CTL_WORDS = CTL_PART + CTL_NPART * CTL_PART_STRIDE

@@ -60,6 +60,14 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+#define GLOBAL __attribute__((address_space(1)))
+
+// a pointer to device memory, in the global address space
+template <class T>
+__device__ __forceinline__ GLOBAL T *gbl(T *p) {
+    return (GLOBAL T *)p;
+}
+
 template <class T>
 __device__ __forceinline__ T *uni_ptr(T *p) {
     const uint64_t v = (uint64_t)p;
@@ -260,26 +268,29 @@ __host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t bmax) {
 
 // A stream-table entry held in scalar registers: every field is read once and made
 // wave-uniform, so buffer resources and loop bounds built from it need no per-lane handling.
+// Its pointers are in the global address space, so accesses through them are global (not flat)
+// instructions: flat accesses also count against the LDS wait counter, and would make every
+// later LDS wait wait for them.
 struct SDesc {
     const uint8_t *elements;
-    const uint32_t *offsets, *lengths, *pparam;
-    uint32_t *agg_count, *agg_min, *agg_max, *out_items;
-    unsigned long long *agg_sum, *lookback, *stats;
+    const GLOBAL uint32_t *offsets, *lengths, *pparam;
+    GLOBAL uint32_t *agg_count, *agg_min, *agg_max, *out_items;
+    GLOBAL unsigned long long *agg_sum, *lookback, *stats;
     uint32_t n_parents, n_elements, B, claim_begin;
 };
 __device__ __forceinline__ SDesc load_sdesc(const StreamDev &s) {
     SDesc d;
     d.elements = uni_ptr((const uint8_t *)s.elements);
-    d.offsets = uni_ptr(s.offsets);
-    d.lengths = uni_ptr(s.lengths);
-    d.pparam = uni_ptr(s.pparam);
-    d.agg_count = uni_ptr(s.agg_count);
-    d.agg_sum = uni_ptr(s.agg_sum);
-    d.agg_min = uni_ptr(s.agg_min);
-    d.agg_max = uni_ptr(s.agg_max);
-    d.out_items = uni_ptr(s.out_items);
-    d.lookback = uni_ptr(s.lookback);
-    d.stats = uni_ptr(s.stats);
+    d.offsets = gbl(uni_ptr(s.offsets));
+    d.lengths = gbl(uni_ptr(s.lengths));
+    d.pparam = gbl(uni_ptr(s.pparam));
+    d.agg_count = gbl(uni_ptr(s.agg_count));
+    d.agg_sum = gbl(uni_ptr(s.agg_sum));
+    d.agg_min = gbl(uni_ptr(s.agg_min));
+    d.agg_max = gbl(uni_ptr(s.agg_max));
+    d.out_items = gbl(uni_ptr(s.out_items));
+    d.lookback = gbl(uni_ptr(s.lookback));
+    d.stats = gbl(uni_ptr(s.stats));
     d.n_parents = uni(s.n_parents);
     d.n_elements = uni(s.n_elements);
     d.B = uni(s.parents_per_claim);
@@ -327,6 +338,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     uint32_t *const s_max = (uint32_t *)(dyn + lay.mx);
 
     const uint32_t t = threadIdx.x;
+    GLOBAL uint32_t *const ctl = gbl(a.ctl);
 
     // stage parameters
     const uint32_t modm = a.param[0] ? a.param[0] : 4u;
@@ -336,7 +348,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     // this launch's epoch (set by the reset kernel before it), as a 24-bit tag in
     // [1, 2^24 - 1] for the look-back words
     const uint32_t epoch_tag =
-        uni(__hip_atomic_load(&a.ctl[CTL_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) % 0xFFFFFFu + 1u;
+        uni(__hip_atomic_load(&ctl[CTL_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) % 0xFFFFFFu + 1u;
 
     // stream of global claim gg: the last with claim_begin <= gg
     auto stream_of = [&](uint32_t gg) -> uint32_t {
@@ -382,49 +394,61 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
         }
     };
-    // Claims.  The launch's claims are split into n_parts contiguous partitions, one per XCD
-    // (workgroups are dispatched round-robin over the XCDs), each with its own counter in its
-    // own cache line, so claim traffic spreads over independent atomics.  A wave first takes
-    // about three quarters of its home partition's claims by its index (claims widx,
+    // Claims.  The launch's claims are split into n_parts contiguous partitions, each served by
+    // the waves of one XCD (workgroups are dispatched round-robin over the 8 XCDs, and wave b's
+    // partition is b mod 64), each with its own counter in its own cache line, so claim traffic
+    // spreads over independent atomics and no counter sees more than a few dozen waves.  A wave first takes
+    // about seven eighths of its home partition's claims by its index (claims widx,
     // widx + Wp, widx + 2 Wp, ... for the partition's Wp waves; no atomic at all), then claims
     // from its home counter, and when that partition is used up, from the other partitions'
-    // counters; a plain read skips a used-up counter without an atomic.
+    // counters, found with one read of all of them.
     const uint32_t n_claims = a.total_claims, np = a.n_parts, n_waves = gridDim.x;
-    const uint32_t home = blockIdx.x % np, widx = blockIdx.x / np;
-    auto p_begin = [&](uint32_t q) -> uint32_t { return (uint32_t)(((uint64_t)n_claims * q) / np); };
-    auto p_waves = [&](uint32_t q) -> uint32_t { return n_waves > q ? (n_waves - 1u - q) / np + 1u : 0u; };
+    const uint32_t np_log = np == 1u ? 0u : 6u;   // n_parts is 1 or CTL_NPART = 64
+    const uint32_t home = blockIdx.x & (np - 1u), widx = blockIdx.x >> np_log;
+    auto p_begin = [&](uint32_t q) -> uint32_t { return (uint32_t)(((uint64_t)n_claims * q) >> np_log); };
+    auto p_waves = [&](uint32_t q) -> uint32_t { return n_waves > q ? ((n_waves - 1u - q) >> np_log) + 1u : 0u; };
     // claims each wave of partition q takes by index (at least two: the two claims in hand)
     auto p_static = [&](uint32_t q) -> uint32_t {
         const uint32_t wq = p_waves(q), size = p_begin(q + 1u) - p_begin(q);
-        return wq ? max(2u, size / 4u * 3u / wq) : 0u;
+        return wq ? max(2u, size / 8u * 7u / wq) : 0u;
     };
     const uint32_t home_static = p_static(home), home_waves = p_waves(home);
-    uint32_t n_static = 0, tried = 0;
+    const uint32_t home_begin = p_begin(home), home_end = p_begin(home + 1u);
+    uint32_t n_static = 0;
+    uint64_t dry = 0;   // partitions found without dynamic claims left
     auto take_claim = [&]() -> uint32_t {
         while (n_static < home_static) {
-            const uint32_t c = p_begin(home) + widx + n_static * home_waves;
+            const uint32_t c = home_begin + widx + n_static * home_waves;
             ++n_static;
-            if (c < p_begin(home + 1u)) return c;
+            if (c < home_end) return c;
             n_static = home_static;
         }
-        while (tried < np) {
-            const uint32_t q = (home + tried) % np;
-            const uint32_t first = p_begin(q) + p_static(q) * p_waves(q), end = p_begin(q + 1u);
-            if (first < end) {
-                uint32_t got = 0xFFFFFFFFu;
-                if (t == 0) {
-                    uint32_t *ctr = &a.ctl[CTL_PART + q * CTL_PART_STRIDE];
-                    if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < end - first) {
-                        const uint32_t k = atomicAdd(ctr, 1u);
-                        if (k < end - first) got = first + k;
-                    }
+        // dynamic claims: the home counter until it runs dry, then one read of every
+        // partition's counter (lane q reads partition q) finds the partitions with claims left
+        while (true) {
+            uint32_t q = home;
+            if ((dry & (1ull << home)) != 0ull) {
+                uint32_t left = 0;
+                if (t < np) {
+                    const uint32_t f = p_begin(t) + p_static(t) * p_waves(t), e2 = p_begin(t + 1u);
+                    left = f < e2 && __hip_atomic_load(&ctl[CTL_PART + t * CTL_PART_STRIDE], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) < e2 - f;
                 }
-                got = uni(got);
-                if (got != 0xFFFFFFFFu) return got;
+                const uint64_t m = __ballot(left) & ~dry;
+                if (!m) return n_claims;   // nothing left
+                q = (uint32_t)__builtin_ctzll(m);
             }
-            ++tried;
+            const uint32_t first = p_begin(q) + p_static(q) * p_waves(q), end = p_begin(q + 1u);
+            uint32_t got = 0xFFFFFFFFu;
+            if (first < end && t == 0) {
+                const uint32_t k = __hip_atomic_fetch_add(&ctl[CTL_PART + q * CTL_PART_STRIDE], 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (k < end - first) got = first + k;
+            }
+            got = uni(got);
+            if (got != 0xFFFFFFFFu) return got;
+            dry |= 1ull << q;
         }
-        return n_claims;   // nothing left
     };
 
     // claims are taken two ahead: g is worked on, g1 is next (its region table in registers)
@@ -509,7 +533,8 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             if (__ballot(bad)) {
                 if (t == 0) {
-                    atomicOr((unsigned int *)&sd.stats[ST_ERROR], 1u);
+                    __hip_atomic_fetch_or((GLOBAL unsigned int *)&sd.stats[ST_ERROR], 1u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
                     if (a.emit_outputs)   // successors of this claim must not wait for it
                         __hip_atomic_store(&sd.lookback[cidx], ((unsigned long long)epoch_tag << 40) | (2ull << 38),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -656,7 +681,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             // own count, flag 2 = inclusive prefix through this claim
             unsigned long long prefix = 0;
             if (t == 0) {
-                unsigned long long *lb = sd.lookback;
+                GLOBAL unsigned long long *lb = sd.lookback;
                 const unsigned long long tagw = (unsigned long long)epoch_tag << 40;
                 const unsigned long long mask38 = (1ull << 38) - 1ull;
                 __hip_atomic_store(&lb[cidx], tagw | (1ull << 38) | (n_out & mask38), __ATOMIC_RELAXED,
@@ -676,7 +701,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             out_rank = ((unsigned long long)uni((uint32_t)(prefix >> 32)) << 32) | uni((uint32_t)prefix);
         }
-        uint32_t *const out_items = sd.out_items;
+        GLOBAL uint32_t *const out_items = sd.out_items;
 
         // ---- node state (all uniform)
         uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;            // data queue heads and tails
@@ -1094,7 +1119,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         if constexpr (TAG) flush_wave(utag);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no staged copy outlives the claim
         order();
-        if (failed && t == 0) atomicOr(&a.ctl[CTL_ERROR], 1u);
+        if (failed && t == 0) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         // ---- end(): one record per parent, written once
         for (uint32_t i = t; i < nb; i += 64u) {
@@ -1104,7 +1129,8 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             if (a.agg_fields & RS_MIN) sd.agg_min[p] = s_min[i];
             if (a.agg_fields & RS_MAX) sd.agg_max[p] = s_max[i];
         }
-        if (a.collect_stats && t < ST_SIGNALS + 3 && stv) atomicAdd(&sd.stats[t], (unsigned long long)stv);
+        if (a.collect_stats && t < ST_SIGNALS + 3 && stv)
+            __hip_atomic_fetch_add(&sd.stats[t], (unsigned long long)stv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         order();
         g = g1;
         g1 = g_next;
@@ -1175,6 +1201,7 @@ bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width) {
 __global__ void __launch_bounds__(64) rs_reset(uint32_t *ctl) {
     const uint32_t t = threadIdx.x;
     if (t < CTL_NPART) ctl[CTL_PART + t * CTL_PART_STRIDE] = 0u;
+    static_assert(CTL_NPART <= 64, "one lane per claim counter");
     if (t == 0) ctl[CTL_EPOCH] += 1u;
 }
 
