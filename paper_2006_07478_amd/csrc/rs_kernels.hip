@@ -106,33 +106,37 @@ __device__ __forceinline__ u32x4 rsrc_words(const void *base, uint32_t bytes) {
 
 #define RS_LDSCOPY(off) "buffer_load_dword %[v], %[r], 0 offen offset:" #off " lds\n\t"
 #define RS_LDSCOPY4(a, b, c, d) RS_LDSCOPY(a) RS_LDSCOPY(b) RS_LDSCOPY(c) RS_LDSCOPY(d)
+#define RS_LDSCOPY_BEGIN "s_nop 2\n\ts_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\ts_nop 0\n\t"
 
 // Copies V rounds of 64 words from the buffer to LDS at lds_base: round k moves word
 // k*64 + lane (the immediate offset advances both addresses).  The copy is written as asm so
 // that the compiler neither orders other LDS accesses behind it nor waits for it: its
 // completion is awaited explicitly (vmcnt) before the words are read.  m0 holds the LDS base
-// and is restored afterwards.
+// and is restored afterwards.  The compiler's hazard checks do not look inside asm, so the
+// wait states are part of it: five between a vector write of the descriptor's scalar
+// registers (a readfirstlane just before) and the loads that read them, and one between the
+// write of m0 and a load into LDS.
 template <int V>
 __device__ __forceinline__ void lds_copy(u32x4 r, uint32_t lds_base, uint32_t voff) {
     uint32_t save;
     if constexpr (V == 1) {
-        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY(0) "s_mov_b32 m0, %[s]"
+        asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY(0) "s_mov_b32 m0, %[s]"
                      : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else if constexpr (V == 2) {
-        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY(0) RS_LDSCOPY(256)
+        asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY(0) RS_LDSCOPY(256)
                      "s_mov_b32 m0, %[s]"
                      : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else if constexpr (V == 4) {
-        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY4(0, 256, 512, 768)
+        asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY4(0, 256, 512, 768)
                      "s_mov_b32 m0, %[s]"
                      : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else if constexpr (V == 8) {
-        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY4(0, 256, 512, 768)
+        asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY4(0, 256, 512, 768)
                      RS_LDSCOPY4(1024, 1280, 1536, 1792) "s_mov_b32 m0, %[s]"
                      : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else {
         static_assert(V == 16, "ensemble rounds");
-        asm volatile("s_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\t" RS_LDSCOPY4(0, 256, 512, 768)
+        asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY4(0, 256, 512, 768)
                      RS_LDSCOPY4(1024, 1280, 1536, 1792) RS_LDSCOPY4(2048, 2304, 2560, 2816)
                      RS_LDSCOPY4(3072, 3328, 3584, 3840) "s_mov_b32 m0, %[s]"
                      : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
@@ -151,10 +155,16 @@ __device__ __forceinline__ uint32_t qslot(uint32_t base, uint32_t i) {
     }
 }
 
-// a where the lane's bit of mask is set, else b (one v_cndmask, never a branch)
+// a where the lane's bit of mask is set, else b (one v_cndmask, never a branch).  The mask is
+// first copied to a scalar register pair of the asm's own: the compiler may otherwise hand
+// over exec itself (a ballot of a condition true on every lane folds to it), and a v_cndmask
+// that takes exec as its lane mask selects wrongly on the upper half of the wave.  The copy
+// also keeps the select clear of the wait states that a vector write of the mask (a compare)
+// would need before a vector read, which the compiler cannot see inside asm.
 __device__ __forceinline__ uint32_t pick(uint64_t mask, uint32_t a, uint32_t b) {
     uint32_t r;
-    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+    uint64_t m;
+    asm("s_mov_b64 %1, %4\n\tv_cndmask_b32 %0, %2, %3, %1" : "=v"(r), "=&s"(m) : "v"(b), "v"(a), "s"(mask));
     return r;
 }
 
@@ -325,7 +335,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     __shared__ uint8_t q1t[TAG ? D1 + 64 : 1];
     __shared__ uint32_t q2v[HAS_E ? D2 + 64 : 1];
     __shared__ uint8_t q2t[(HAS_E && TAG) ? D2 + 64 : 1];
-    __shared__ uint32_t fsl[BYTES ? 1 : 2 * EW];   // two staging slots for the enumerating node
+    __shared__ uint32_t fsl[BYTES ? 1 : EW];   // staging slot for the enumerating node's next ensemble
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
 
     const Dyn lay = dyn_layout(KIND, a.bmax);
@@ -359,13 +369,19 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         }
         return uni(lo);
     };
-    // the stream-table entry last read (consecutive claims usually share a stream)
-    SDesc sdc;
-    uint32_t sdc_idx = 0xFFFFFFFFu;
+    // the stream-table entry last used, copied to LDS (consecutive claims usually share a
+    // stream); fields are read from it where they are needed, which keeps scalar registers free
+    __shared__ StreamDev sdl;
+    uint32_t sdl_idx = 0xFFFFFFFFu;
     auto ensure_sd = [&](uint32_t si) {
-        if (si != sdc_idx) {
-            sdc = load_sdesc(a.streams[si]);
-            sdc_idx = si;
+        if (si != sdl_idx) {
+            constexpr uint32_t NW = sizeof(StreamDev) / 4u;
+            static_assert(sizeof(StreamDev) % 4u == 0u && NW <= 64u, "one word per lane");
+            uint32_t v = 0;
+            if (t < NW) v = gbl((const uint32_t *)&a.streams[si])[t];
+            if (t < NW) ((uint32_t *)&sdl)[t] = v;
+            order();
+            sdl_idx = si;
         }
     };
     // this lane's share of the region table of claim gg (loads only; consumed a claim later)
@@ -374,7 +390,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         for (uint32_t q = 0; q < R; ++q) r.off[q] = r.len[q] = r.ctx[q] = 0;
         if (gg >= a.total_claims) return;
         ensure_sd(stream_of(gg));
-        const SDesc &sd = sdc;
+        const SDesc sd = load_sdesc(sdl);
         const uint32_t B = sd.B;
         const uint32_t p0 = (gg - sd.claim_begin) * B;
         const uint32_t nb = min(B, sd.n_parents - p0);
@@ -463,7 +479,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         load_claim(g1, nxt);                    // consumed at the next claim
 
         ensure_sd(stream_of(g));
-        const SDesc &sd = sdc;
+        const SDesc sd = load_sdesc(sdl);
         const uint8_t *const elems = sd.elements;
         const uint32_t B = sd.B;
         const uint32_t cidx = g - sd.claim_begin;
@@ -551,22 +567,20 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // text: the whole byte array (addresses fit in 32 bits); word loads near its end fall
         // back to bytes, so no load depends on the range check for its value
         const __amdgpu_buffer_rsrc_t rtext = rsrc(elems, BYTES ? sd.n_elements : 0u);
-        // u32 elements: the ensemble starting at position pos is copied to a staging slot by
+        // u32 elements: the ensemble starting at position pos is copied to the staging slot by
         // direct buffer->LDS loads (item k*64 + lane to word k*64 + lane; positions past vend
-        // read as zero).  Two slots alternate: a firing requests the ensemble of the firing after
-        // next into the slot it has just read, so a copy has two firings' time to land even when
-        // the enumerating node fires twice in a row.  Completion is awaited explicitly: a slot
-        // whose copy is older than the other slot's needs all but the newest V loads done.
-        uint32_t spos0 = 0xFFFFFFFFu, spos1 = 0xFFFFFFFFu;   // position each slot holds or receives
-        uint32_t last = 0;                                    // slot whose copy was issued last
-        auto stage = [&](uint32_t pos, uint32_t slot) {
+        // read as zero).  A firing requests the next firing's ensemble as soon as it has taken
+        // the slot's contents into registers, so the copy overlaps whatever fires in between;
+        // its completion is awaited explicitly (vmcnt) before the slot is read.  One slot, not
+        // two: the LDS it saves buys more resident waves, which hide the latency better.
+        uint32_t spos = 0xFFFFFFFFu;   // position whose ensemble the slot holds or receives
+        auto stage = [&](uint32_t pos) {
             if constexpr (!BYTES) {
-                if (slot) spos1 = 0xFFFFFFFFu; else spos0 = 0xFFFFFFFFu;
+                spos = 0xFFFFFFFFu;
                 if (pos < vend) {
-                    lds_copy<V>(rsrc_words(elems + (size_t)pos * 4u, min(EW, vend - pos) * 4u),
-                                uni(lds_addr(fsl) + slot * EW * 4u), t * 4u);
-                    if (slot) spos1 = pos; else spos0 = pos;
-                    last = slot;
+                    lds_copy<V>(rsrc_words(elems + (size_t)pos * 4u, min(EW, vend - pos) * 4u), uni(lds_addr(fsl)),
+                                t * 4u);
+                    spos = pos;
                 }
             }
         };
@@ -741,7 +755,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             (uint32_t)min(8ull * ((unsigned long long)(vend - vbeg) + nb) + 64ull, 0xFFFFFFFFull);
         uint32_t iters = 0;
 
-        stage(fpos, 0);
+        stage(fpos);
 
         // per-lane flush of the accumulator into region slot j (LDS atomics)
         auto flush_lane = [&](uint32_t j) {
@@ -849,6 +863,17 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if constexpr (KIND == RS_HASH_EXPAND) c[k] = q1a[pos]; else c[k] = 1u;
                 if constexpr (TAG) tg[k] = q1t[pos]; else tg[k] = 0u;
             }
+            // output counts of every round (they do not depend on the word lengths below)
+            uint64_t b0[V], b1[V];
+            uint32_t total = 0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const bool act = FULL || (uint32_t)k * 64u + t < e;
+                const uint32_t nout = act ? c[k] : 0u;
+                b0[k] = __ballot(nout & 1u);
+                b1[k] = KE == 3u ? __ballot(nout & 2u) : 0ull;
+                total += (uint32_t)__popcll(b0[k]) + 2u * (uint32_t)__popcll(b1[k]);
+            }
             if constexpr (BYTES) {
                 // word length: run of non-space bytes from the word's start, within its line,
                 // four bytes at a time
@@ -882,34 +907,44 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             // The firing takes the longest prefix of the ensemble whose outputs fit the free
             // slots (the scheduler guarantees room for the first item's worst case); offsets are
-            // exclusive prefixes in ensemble order, so the items that fit form a prefix.
+            // exclusive prefixes in ensemble order, so the items that fit form a prefix.  When the
+            // whole ensemble's outputs fit (the usual case) no item needs the room test.
             const uint32_t room = D2 - (t2 - h2);
-            uint32_t run = 0, taken = 0, made = 0;
+            uint32_t taken = 0, made = 0;
+            auto write_rounds = [&](auto fit_all) {
+                constexpr bool FIT = decltype(fit_all)::value;
+                uint32_t run = 0;
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const bool act = FULL || (uint32_t)k * 64u + t < e;
-                const uint32_t nout = act ? c[k] : 0u;
-                const uint64_t b0 = __ballot(nout & 1u);
-                uint32_t within = rank_below(b0), pc = (uint32_t)__popcll(b0);
-                uint64_t b1 = 0;
-                if constexpr (KE == 3u) {
-                    b1 = __ballot(nout & 2u);
-                    within += 2u * rank_below(b1);
-                    pc += 2u * (uint32_t)__popcll(b1);
-                }
-                const uint32_t off = run + within;
-                const uint64_t fits = __ballot(act && off + nout <= room);
-                taken += (uint32_t)__popcll(fits);
-                made += (uint32_t)__popcll(b0 & fits) + 2u * (uint32_t)__popcll(b1 & fits);
+                for (int k = 0; k < V; ++k) {
+                    const bool act = FULL || (uint32_t)k * 64u + t < e;
+                    const uint32_t nout = act ? c[k] : 0u;
+                    uint32_t within = rank_below(b0[k]);
+                    if constexpr (KE == 3u) within += 2u * rank_below(b1[k]);
+                    const uint32_t off = run + within;
+                    const uint32_t slot0 = qslot<D2>(t2w, off);   // first child's slot
+                    uint64_t fits = 0;
+                    if constexpr (!FIT) {
+                        fits = __ballot(act && off + nout <= room);
+                        taken += (uint32_t)__popcll(fits);
+                        made += (uint32_t)__popcll(b0[k] & fits) + 2u * (uint32_t)__popcll(b1[k] & fits);
+                    }
 #pragma unroll
-                for (uint32_t ch = 0; ch < KE; ++ch) {
-                    const uint32_t pos = pick(__ballot(ch < nout) & fits, qslot<D2>(t2w, off + ch), D2 + t);
-                    // child ch of x leaves as its pre-image x ^ K(ch+1) (hash kind); a word as its length
-                    q2v[pos] = KIND == RS_HASH_EXPAND ? x[k] ^ salt_key(ch + 1u) : x[k];
-                    if constexpr (TAG) q2t[pos] = (uint8_t)tg[k];
+                    for (uint32_t ch = 0; ch < KE; ++ch) {
+                        const uint32_t sl = ch == 0u ? slot0 : qslot<D2>(slot0, ch);
+                        const uint64_t m = FIT ? __ballot(ch < nout) : (__ballot(ch < nout) & fits);
+                        const uint32_t pos = pick(m, sl, D2 + t);
+                        // child ch of x leaves as its pre-image x ^ K(ch+1) (hash kind); a word as its length
+                        q2v[pos] = KIND == RS_HASH_EXPAND ? x[k] ^ salt_key(ch + 1u) : x[k];
+                        if constexpr (TAG) q2t[pos] = (uint8_t)tg[k];
+                    }
+                    run += (uint32_t)__popcll(b0[k]) + 2u * (uint32_t)__popcll(b1[k]);
                 }
-                run += pc;
-            }
+                if constexpr (FIT) {
+                    taken = e;
+                    made = total;
+                }
+            };
+            if (total <= room) write_rounds(BoolC<true>{}); else write_rounds(BoolC<false>{});
             h1 += taken;
             t2 += made;
             t2w = qslot<D2>(t2w, made);
@@ -930,21 +965,11 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) reg[k] = fj;
             }
-            uint32_t slot = 0;
             if constexpr (!BYTES) {
-                if (spos0 == fpos) {
-                    slot = 0;
-                } else if (spos1 == fpos) {
-                    slot = 1;
-                } else {
-                    slot = last ^ 1u;
-                    stage(fpos, slot);
-                }
-                // the slot's copy has landed: if the other slot's copy is newer, only its V
-                // loads may still be outstanding
-                if (last != slot) wait_vmem<V>(); else wait_vmem<0>();
+                if (spos != fpos) stage(fpos);
+                wait_vmem<0>();   // the slot's copy has landed
 #pragma unroll
-                for (int k = 0; k < V; ++k) x[k] = fsl[slot * EW + k * 64 + t];
+                for (int k = 0; k < V; ++k) x[k] = fsl[k * 64 + t];
             } else {
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = 0;
@@ -974,23 +999,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     jnext = jlo + 1u < nb ? uni((BYTES ? SX : VT)[jlo + 1u]) : 0xFFFFFFFFu;
                 }
             }
-            if constexpr (!BYTES) {
-                // the next firing starts at p1 (its copy is in the other slot, or requested now);
-                // the one after starts at p2 and goes to the slot just read
-                const uint32_t p1 = fpos + e;
-                uint32_t p2 = p1;
-                if (p1 < vend) {
-                    uint32_t r1 = vend;   // end of the ensemble that starts at p1
-                    if constexpr (!TAG) {
-                        uint32_t j = fj;
-                        r1 = rend;
-                        while (r1 <= p1 && j + 1u < nb) r1 = uni(VT[++j + 1u]);
-                    }
-                    p2 = p1 + min(EW, r1 - p1);
-                }
-                if ((slot ? spos0 : spos1) != p1) stage(p1, slot ^ 1u);
-                stage(p2, slot);
-            }
+            if constexpr (!BYTES) stage(fpos + e);   // the slot's contents are in registers
             t1 += run;
             fpos += e;
             stat(ST_FIRINGS + 0, 1u);
@@ -1122,15 +1131,19 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         if (failed && t == 0) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         // ---- end(): one record per parent, written once
-        for (uint32_t i = t; i < nb; i += 64u) {
-            const uint32_t p = p0 + i;
-            if (a.agg_fields & RS_COUNT) sd.agg_count[p] = s_cnt[i];
-            if (a.agg_fields & RS_SUM) sd.agg_sum[p] = s_sum[i];
-            if (a.agg_fields & RS_MIN) sd.agg_min[p] = s_min[i];
-            if (a.agg_fields & RS_MAX) sd.agg_max[p] = s_max[i];
+        {
+            const SDesc se = load_sdesc(sdl);   // read here, after the scheduler loop
+            for (uint32_t i = t; i < nb; i += 64u) {
+                const uint32_t p = p0 + i;
+                if (a.agg_fields & RS_COUNT) se.agg_count[p] = s_cnt[i];
+                if (a.agg_fields & RS_SUM) se.agg_sum[p] = s_sum[i];
+                if (a.agg_fields & RS_MIN) se.agg_min[p] = s_min[i];
+                if (a.agg_fields & RS_MAX) se.agg_max[p] = s_max[i];
+            }
+            if (a.collect_stats && t < ST_SIGNALS + 3 && stv)
+                __hip_atomic_fetch_add(&se.stats[t], (unsigned long long)stv, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (a.collect_stats && t < ST_SIGNALS + 3 && stv)
-            __hip_atomic_fetch_add(&sd.stats[t], (unsigned long long)stv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         order();
         g = g1;
         g1 = g_next;
