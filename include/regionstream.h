@@ -86,6 +86,8 @@ enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
 /* rs_pipeline_desc.flags */
 #define RS_COLLECT_STATS 1u   /* count firings, items, full ensembles and signals per node */
 #define RS_NO_GRAPH      2u   /* do not capture/replay the launch as a HIP graph */
+#define RS_TIME_KERNEL   4u   /* time the pipeline kernel of every run with HIP events (kernel_times);
+                                 implies RS_NO_GRAPH */
 
 typedef struct rs_pipeline rs_pipeline;   /* opaque, library-owned */
 
@@ -102,7 +104,7 @@ typedef struct rs_pipeline rs_pipeline;   /* opaque, library-owned */
  *                   stage, a power of two >= 2*ensemble_width (the stage maxima need room for
  *                   k*w outputs plus signal slots, §3.2 fireability)
  *   emit_outputs    1 = also produce the ordered surviving-item stream (read_outputs)
- *   flags           RS_COLLECT_STATS | RS_NO_GRAPH
+ *   flags           RS_COLLECT_STATS | RS_NO_GRAPH | RS_TIME_KERNEL
  *   hbm_budget_bytes  0 = unlimited; else streams are admitted to a run only while the device
  *                   footprint of admitted streams stays within the budget
  *   param           stage parameters (RS_MODFILTER: modulus, residue)
@@ -211,6 +213,15 @@ int read_outputs(rs_pipeline *p, uint64_t stream_id, uint32_t *out, uint64_t cap
 
 /* Device statistics of one stream (zeros unless RS_COLLECT_STATS).  Errors as read_aggregates. */
 int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out);
+
+/* Measurement aid (pipelines created with RS_TIME_KERNEL): the device time of the pipeline
+ * kernel of every run and run_again since the previous call, in launch order, in
+ * milliseconds.  Each launch records a pair of HIP events on its own stream, directly before
+ * and after the pipeline kernel (the small reset kernel in front of it is outside the pair);
+ * this call waits for them.  At most cap values go to ms (caller-owned host memory, may be NULL
+ * when cap is 0); *n receives how many launches were timed, and all of them are consumed.
+ * Errors: RS_EINVAL (NULL p or n, or the pipeline lacks RS_TIME_KERNEL), RS_EDEVICE. */
+int kernel_times(rs_pipeline *p, float *ms, uint32_t cap, uint32_t *n);
 
 /* Free a finished stream's device state; its id becomes unknown.  Errors: RS_ENOTFOUND,
  * RS_ESTATE (still running). */

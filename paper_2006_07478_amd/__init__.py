@@ -22,14 +22,14 @@ RS_COUNT, RS_SUM, RS_MIN, RS_MAX = 1, 2, 4, 8
 RS_MEM_HOST, RS_MEM_DEVICE = 0, 1
 RS_RUN_SYNC, RS_RUN_ASYNC, RS_RUN_PER_STREAM = 0, 1, 2
 RS_READ_BLOCK, RS_NONBLOCK, RS_READ_DEVICE, RS_READ_RELEASE = 0, 1, 2, 4
-RS_COLLECT_STATS, RS_NO_GRAPH = 1, 2
+RS_COLLECT_STATS, RS_NO_GRAPH, RS_TIME_KERNEL = 1, 2, 4
 
 STATUS_NAMES = {0: "RS_OK", -1: "RS_EINVAL", -2: "RS_ENOMEM", -3: "RS_EDEVICE", -4: "RS_EBUDGET",
                 -5: "RS_ENOTREADY", -6: "RS_ESTATE", -7: "RS_ENOTFOUND"}
 
 ABI_FUNCTIONS = ["pipeline_create", "pipeline_set_stream", "stream_push", "run", "run_again",
-                 "read_aggregates", "read_outputs", "rs_stats", "stream_release", "serve", "hbm_probe", "pipeline_destroy",
-                 "rs_last_error"]
+                 "read_aggregates", "read_outputs", "rs_stats", "kernel_times", "stream_release", "serve", "hbm_probe",
+                 "pipeline_destroy", "rs_last_error"]
 
 
 class RsError(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
         L.read_aggregates.argtypes = [vp, u64, ctypes.POINTER(rs_agg_view), u32]
         L.read_outputs.argtypes = [vp, u64, vp, u64, ctypes.POINTER(u64), u32]
         L.rs_stats.argtypes = [vp, u64, ctypes.POINTER(rs_stats_t)]
+        L.kernel_times.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
         L.stream_release.argtypes = [vp, u64]
         L.serve.argtypes = [vp, ctypes.POINTER(rs_request), u64, ctypes.POINTER(rs_agg_view),
                             ctypes.POINTER(rs_request_timing), u32]
@@ -155,6 +156,13 @@ def rs_stats(p, stream_id):
     st = rs_stats_t()
     _check(lib().rs_stats(p, stream_id, ctypes.byref(st)))
     return st
+
+
+def kernel_times(p, cap=4096):
+    ms = np.zeros(max(cap, 1), np.float32)
+    n = ctypes.c_uint32(0)
+    _check(lib().kernel_times(p, ms.ctypes.data, cap, ctypes.byref(n)))
+    return ms[:min(n.value, cap)].tolist()
 
 
 def stream_release(p, stream_id):
@@ -293,6 +301,10 @@ class Pipeline:
 
     def stats(self, sid):
         return rs_stats(self.h, sid)
+
+    def kernel_times(self, cap=4096):
+        """Pipeline-kernel device times (ms) of the launches since the last call (RS_TIME_KERNEL)."""
+        return kernel_times(self.h, cap)
 
     def serve(self, requests, arrivals, per_stream=False, read=True):
         """Run the native serving loop over requests = [(offsets, elements[, lengths, parent_param])]

@@ -68,8 +68,10 @@ uint32_t lanes_of(uint32_t ensemble_width);
 // Most parents one claim may hold (the region table has 256 entries, the last is the end offset).
 inline uint32_t claim_parents_max(uint32_t ensemble_width) { return ensemble_width ? 255u : 0u; }
 bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width);
+// Enqueues the reset kernel, then the pipeline kernel, on stream.  Non-null ev_begin/ev_end
+// (HIP events) are recorded directly before and after the pipeline kernel.
 int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a,
-                    uint32_t grid, void *stream);
+                    uint32_t grid, void *stream, void *ev_begin = nullptr, void *ev_end = nullptr);
 int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t bmax);
 // Bytes of per-claim LDS (region table and aggregate slots) for claims of up to bmax parents.
 uint32_t dyn_lds_bytes(uint32_t kind, uint32_t bmax);

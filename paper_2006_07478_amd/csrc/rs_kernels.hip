@@ -1219,12 +1219,17 @@ __global__ void __launch_bounds__(64) rs_reset(uint32_t *ctl) {
 }
 
 int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a, uint32_t grid,
-                    void *stream) {
+                    void *stream, void *ev_begin, void *ev_end) {
     KernelFn k = pick(kind, strategy, width);
     if (!k) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL(rs_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, a.ctl);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), dyn_lds_bytes(kind, a.bmax), (hipStream_t)stream, a);
-    return (int)hipGetLastError();
+    const hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(rs_reset, dim3(1), dim3(64), 0, st, a.ctl);
+    hipError_t e = hipSuccess;
+    if (ev_begin && (e = hipEventRecord((hipEvent_t)ev_begin, st)) != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), dyn_lds_bytes(kind, a.bmax), st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+    if (ev_end && (e = hipEventRecord((hipEvent_t)ev_end, st)) != hipSuccess) return (int)e;
+    return (int)hipSuccess;
 }
 
 int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t bmax) {

@@ -140,6 +140,8 @@ struct rs_pipeline {
     std::map<uint64_t, std::unique_ptr<Stream>> streams;
     std::map<uint64_t, std::unique_ptr<Batch>> batches;
     uint64_t last_batch = 0;
+    // RS_TIME_KERNEL: event pairs around launched pipeline kernels (oldest first), and spares
+    std::deque<std::pair<hipEvent_t, hipEvent_t>> timed, spare_events;
 };
 
 namespace {
@@ -322,14 +324,40 @@ int prepare_lookback(rs_pipeline *p, Batch &b) {
     return RS_OK;
 }
 
-int launch_batch(rs_pipeline *p, Batch &b, bool graph) {
+// A pair of timing events, reused once kernel_times has read it.
+int timing_events(rs_pipeline *p, std::pair<hipEvent_t, hipEvent_t> *ev) {
+    if (!p->spare_events.empty()) {
+        *ev = p->spare_events.front();
+        p->spare_events.pop_front();
+        return RS_OK;
+    }
+    HIP_OR(hipEventCreate(&ev->first), RS_EDEVICE);
+    if (hipEventCreate(&ev->second) != hipSuccess) {
+        (void)hipEventDestroy(ev->first);
+        return fail(RS_EDEVICE, "hipEventCreate failed");
+    }
+    return RS_OK;
+}
+
+// timed: a run of the caller's (not an autotune probe) on a pipeline with RS_TIME_KERNEL
+int launch_batch(rs_pipeline *p, Batch &b, bool graph, bool timed = false) {
     if (!b.total_claims) {
         HIP_OR(hipEventRecord(b.done, b.lane), RS_EDEVICE);
         return RS_OK;
     }
     int rc = prepare_lookback(p, b);
     if (rc) return rc;
-    if (graph) {
+    timed = timed && (p->d.flags & RS_TIME_KERNEL);
+    if (timed) {
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if ((rc = timing_events(p, &ev))) return rc;
+        rc = rs::launch_pipeline(p->d.kind, b.strategy, b.width, b.args, b.grid, b.lane, ev.first, ev.second);
+        if (rc) {
+            p->spare_events.push_back(ev);
+            return fail(RS_EDEVICE, "kernel launch failed: %s", hipGetErrorString((hipError_t)rc));
+        }
+        p->timed.push_back(ev);
+    } else if (graph) {
         if (!b.graph) {
             hipGraph_t g = nullptr;
             HIP_OR(hipStreamBeginCapture(b.lane, hipStreamCaptureModeThreadLocal), RS_EDEVICE);
@@ -476,7 +504,7 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
         if (w && q != 2 * w) return fail(RS_EINVAL, "queue_depth %u: this build sizes queues at 2 * ensemble_width", q);
     }
     if (d->emit_outputs > 1) return fail(RS_EINVAL, "emit_outputs must be 0 or 1");
-    if (d->flags & ~3u) return fail(RS_EINVAL, "unknown pipeline flags");
+    if (d->flags & ~7u) return fail(RS_EINVAL, "unknown pipeline flags");
     if (d->kind == RS_MODFILTER && d->param[0] != 0 && d->param[1] >= d->param[0])
         return fail(RS_EINVAL, "residue must be smaller than the modulus");
 
@@ -633,7 +661,7 @@ int launch_streams(rs_pipeline *p, const std::vector<Stream *> &sel, bool per_st
         const uint64_t bid = p->next_batch++;
         std::unique_ptr<Batch> b;
         if ((rc = make_batch(p, grp, bid, false, b))) return rc;
-        if ((rc = launch_batch(p, *b, false))) return rc;
+        if ((rc = launch_batch(p, *b, false, true))) return rc;
         for (Stream *s : grp) {
             s->state = S_LAUNCHED;
             s->batch = bid;
@@ -685,8 +713,8 @@ RS_API int run_again(rs_pipeline *p, uint32_t flags) {
     if (it == p->batches.end()) return fail(RS_ESTATE, "no batch has run on this pipeline");
     Batch &b = *it->second;
     if (p->user_stream) b.lane = p->user_stream;
-    const bool graph = !(p->d.flags & (RS_NO_GRAPH | RS_COLLECT_STATS));
-    int rc = launch_batch(p, b, graph);
+    const bool graph = !(p->d.flags & (RS_NO_GRAPH | RS_COLLECT_STATS | RS_TIME_KERNEL));
+    int rc = launch_batch(p, b, graph, true);
     if (rc) return rc;
     for (uint64_t id : b.ids) {
         auto si = p->streams.find(id);
@@ -934,11 +962,36 @@ RS_API int hbm_probe(const void *src, void *dst, uint64_t bytes, void *hip_strea
     return RS_OK;
 }
 
+RS_API int kernel_times(rs_pipeline *p, float *ms, uint32_t cap, uint32_t *n) {
+    g_err.clear();
+    if (!p || !n) return fail(RS_EINVAL, "NULL argument");
+    if (!(p->d.flags & RS_TIME_KERNEL)) return fail(RS_EINVAL, "the pipeline was created without RS_TIME_KERNEL");
+    if (cap && !ms) return fail(RS_EINVAL, "NULL ms with cap > 0");
+    uint32_t k = 0;
+    while (!p->timed.empty()) {
+        const auto ev = p->timed.front();
+        float t = 0.f;
+        HIP_OR(hipEventSynchronize(ev.second), RS_EDEVICE);
+        HIP_OR(hipEventElapsedTime(&t, ev.first, ev.second), RS_EDEVICE);
+        p->timed.pop_front();
+        p->spare_events.push_back(ev);
+        if (k < cap) ms[k] = t;
+        ++k;
+    }
+    *n = k;
+    return RS_OK;
+}
+
 RS_API int pipeline_destroy(rs_pipeline *p) {
     if (!p) return RS_OK;
     if (p->user_stream) (void)hipStreamSynchronize(p->user_stream);
     for (auto &h : p->own)
         if (h) (void)hipStreamSynchronize(h);
+    for (auto *q : {&p->timed, &p->spare_events})
+        for (auto &ev : *q) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     p->batches.clear();
     p->streams.clear();
     for (auto &h : p->own)

@@ -386,3 +386,34 @@ def test_serving_rejects_a_request_larger_than_the_budget():
         with pytest.raises(rs.RsError) as ei:
             p.serve([(o, v)], [0.0])
         assert ei.value.code == rs.RS_EBUDGET
+
+
+def test_kernel_times_cover_every_timed_launch():
+    """RS_TIME_KERNEL: one device time per run/run_again, in launch order, inside the host-side
+    span of the launches, and the timed launches still compute the oracle's results."""
+    import time
+    import torch
+    say("kernel times")
+    n, L = 1 << 20, 256
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(7, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_SIGNAL, ensemble_width=128, flags=rs.RS_TIME_KERNEL) as p:
+        sid = p.push(offsets, vals)
+        p.run()
+        first = p.kernel_times()
+        assert len(first) == 1 and first[0] > 0.0
+        assert p.kernel_times() == []   # consumed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            p.run_again(rs.RS_RUN_ASYNC)
+        got_t = p.kernel_times()
+        span_ms = (time.perf_counter() - t0) * 1e3
+        assert len(got_t) == 5 and all(t > 0.0 for t in got_t)
+        assert sum(got_t) <= span_ms
+        check(p.read(sid), ref, where="timed launches")
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=128) as p:
+        with pytest.raises(rs.RsError) as ei:
+            p.kernel_times()
+        assert ei.value.code == rs.RS_EINVAL
