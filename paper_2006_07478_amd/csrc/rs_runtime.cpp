@@ -388,9 +388,24 @@ int batch_error(Batch &b) {
     return RS_OK;
 }
 
-// Time every candidate configuration on (a prefix of) stream s and keep the fastest.
-int autotune(rs_pipeline *p, Stream *s) {
-    const int bucket = length_bucket(s->mean_len);
+// Time every candidate configuration on a probe batch that stands for the selection and keep the
+// fastest.  One launch runs one configuration for all of its streams, so the probe is the
+// selection itself, or, above about 2^25 elements, every k-th stream of it in push order (each
+// stream probed on a prefix of at most 2^25 elements): a mix of short- and long-region streams
+// is tuned as a mix.  The cache key is the probe's mean region length, kept apart for mixes.
+int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
+    constexpr uint64_t kProbeElems = 1ull << 25;
+    uint64_t total = 0;
+    for (Stream *s : sel) total += s->n_elements;
+    std::vector<Stream *> probe;
+    const size_t step = total > kProbeElems ? (size_t)std::min<uint64_t>(sel.size(), total / kProbeElems + 1) : 1;
+    for (size_t i = 0; i < sel.size(); i += step) probe.push_back(sel[i]);
+    double covered = 0, parents = 0;
+    for (Stream *s : probe) {
+        covered += s->mean_len * s->n_parents;
+        parents += s->n_parents;
+    }
+    const int bucket = length_bucket(parents > 0 ? covered / parents : 0.0) + (sel.size() > 1 ? 1000 : 0);
     const uint32_t want_s = p->d.strategy, want_w = p->d.ensemble_width;
     uint32_t cs = 0, cw = 0;
     if (cache_lookup(p->d.kind, p->d.emit_outputs, bucket, &cs, &cw) && (want_s == RS_AUTO || want_s == cs) &&
@@ -412,7 +427,7 @@ int autotune(rs_pipeline *p, Stream *s) {
             p->strategy = strat;
             p->width = w;
             std::unique_ptr<Batch> b;
-            if ((rc = make_batch(p, {s}, 0, true, b))) break;
+            if ((rc = make_batch(p, probe, 0, true, b))) break;
             if ((rc = launch_batch(p, *b, false))) break;   // warm-up
             if (hipEventRecord(e0, b->lane) != hipSuccess) { rc = fail(RS_EDEVICE, "event record"); break; }
             for (int r = 0; r < 2 && rc == RS_OK; ++r) rc = launch_batch(p, *b, false);
@@ -644,10 +659,7 @@ int launch_streams(rs_pipeline *p, const std::vector<Stream *> &sel, bool per_st
     if (sel.empty()) return RS_OK;
     int rc;
     if (!p->configured) {
-        Stream *probe = sel[0];
-        for (Stream *s : sel)
-            if (s->n_elements > probe->n_elements) probe = s;
-        if ((rc = autotune(p, probe))) return rc;
+        if ((rc = autotune(p, sel))) return rc;
         p->configured = true;
     }
     std::vector<std::vector<Stream *>> groups;
