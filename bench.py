@@ -94,7 +94,7 @@ def time_config(rs, torch, stream, offsets, copies, strategy, width, steps, warm
     ms = e0.elapsed_time(e1) / steps
     kt = [t for p, _ in pipes for t in p.kernel_times()]
     assert len(kt) == steps, (len(kt), steps)
-    kernel_ms = sum(kt) / len(kt)
+    kernel_ms = {"mean": sum(kt) / len(kt), "median": float(np.median(kt)), "min": min(kt)}
     st = pipes[0][0].stats(pipes[0][1]) if stats else None
     for p, _ in pipes:
         p.close()
@@ -119,7 +119,8 @@ def probe_copy(rs, torch, stream, nbytes=1 << 30, reps=10):
     return {"copy_bytes": 2 * nbytes, "ms": round(ms, 4), "GB_per_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
-def serving(rs, torch, stream, n_streams=512, rho=0.8, budget=2 << 30):
+def serving(rs, torch, stream, n_streams=512, rhos=(0.5, 0.8, 1.2), headline_rho=0.8, arrival_seeds=(6, 7, 8),
+            budget=2 << 30):
     """512 streams of the serving workload (log-uniform sizes 1e3..1e7, log-uniform mean region
     length 1..4096, hash/expand pipeline).
 
@@ -127,7 +128,8 @@ def serving(rs, torch, stream, n_streams=512, rho=0.8, budget=2 << 30):
          on the same HIP stream (replayed, event-timed).
     serve: the native request loop on host-memory requests under an HBM budget; capacity is
          measured with every request arriving at once, then requests arrive as a Poisson process
-         at rho times that capacity; latency is completion minus arrival (host clock).
+         at rho times that capacity (rho 0.5, 0.8, 1.2; three arrival seeds each); latency is
+         completion minus arrival (host clock), p50/p99 over all requests of the three seeds.
     """
     import workloads
     n, m = workloads.stream_shapes(seed=5, n_streams=n_streams)
@@ -175,22 +177,53 @@ def serving(rs, torch, stream, n_streams=512, rho=0.8, budget=2 << 30):
     del dev
 
     # --- end to end: the request loop on host-memory requests
-    def run_serve(arrivals, per_stream):
-        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=width, hbm_budget_bytes=budget) as p:
-            _, tim = p.serve(reqs, arrivals, per_stream=per_stream)
-        lat = np.array([t["completed"] - t["arrival"] for t in tim])
-        span = max(t["completed"] for t in tim) - min(t["arrival"] for t in tim)
+    def run_serve(arrival_sets, per_stream):
+        lat, rates, launches = [], [], 0
+        for arrivals in arrival_sets:
+            with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=width,
+                             hbm_budget_bytes=budget) as p:
+                _, tim = p.serve(reqs, arrivals, per_stream=per_stream)
+            lat += [t["completed"] - t["arrival"] for t in tim]
+            span = max(t["completed"] for t in tim) - min(t["arrival"] for t in tim)
+            rates.append(total / span)
+            launches += len({t["batch"] for t in tim})
+        lat = np.array(lat)
         return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                "elements_per_s": total / span, "launches": len({t["batch"] for t in tim})}
+                "elements_per_s": float(np.mean(rates)), "launches": launches, "requests": len(lat)}
 
-    sat = run_serve(np.zeros(n_streams), False)
+    sat = run_serve([np.zeros(n_streams)], False)
     capacity = sat["elements_per_s"]
-    rate = rho * capacity / (total / n_streams)
-    arrivals = workloads.arrivals(6, n_streams, rate)
-    out["serve"] = {"capacity_elements_per_s": capacity, "rho": rho, "arrival_rate_per_s": rate,
-                    "batched": run_serve(arrivals, False), "per_stream": run_serve(arrivals, True)}
+    by_rho = {}
+    for rho in rhos:
+        rate = rho * capacity / (total / n_streams)
+        sets = [workloads.arrivals(seed, n_streams, rate) for seed in arrival_seeds]
+        by_rho[str(rho)] = {"arrival_rate_per_s": rate, "batched": run_serve(sets, False),
+                            "per_stream": run_serve(sets, True)}
+        print(f"[bench] serve rho={rho}: {json.dumps(by_rho[str(rho)])}", file=sys.stderr, flush=True)
+    head = by_rho[str(headline_rho)]
+    out["serve"] = {"capacity_elements_per_s": capacity, "rho": headline_rho, "arrival_seeds": list(arrival_seeds),
+                    "arrival_rate_per_s": head["arrival_rate_per_s"], "batched": head["batched"],
+                    "per_stream": head["per_stream"], "by_rho": by_rho}
     return out
+
+
+def host_info():
+    """CPU model and thread counts of the machine the bench runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"host_cpu": model, "host_logical_cpus": os.cpu_count(), "host_usable_cpus": usable}
 
 
 def cpu_baseline(L, budget_s=12.0):
@@ -208,9 +241,44 @@ def cpu_baseline(L, budget_s=12.0):
         t = time.perf_counter() - t0
         if t >= budget_s or reps >= 512:
             break
-    return {"value": reps * n / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} runs of 2^22 elements (regions of {L}) of the same generator, "
-                      f"single-threaded serial oracle, {t:.1f} s"}
+    out = {"value": reps * n / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
+           "sample": f"{reps} runs of 2^22 elements (regions of {L}) of the same generator, "
+                     f"single-threaded serial oracle, {t:.1f} s"}
+    out.update(host_info())
+    return out
+
+
+def cpu_baseline_threads(L, budget_s=6.0):
+    """The same serial oracle function on T contiguous parent ranges at once (one thread each,
+    T = the job's CPU share); the concatenated records must equal the serial run's."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    import workloads
+    n = 1 << 24
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(2, n)
+    # the job's CPU share: OMP_NUM_THREADS where the host sets it, never more than 16 threads
+    T = max(1, min(host_info()["host_usable_cpus"], int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16))
+    P = len(offsets) - 1
+    cuts = [P * i // T for i in range(T + 1)]
+    parts = [(offsets[a:b + 1] - offsets[a], vals[offsets[a]:offsets[b]]) for a, b in zip(cuts, cuts[1:])]
+    run_part = lambda ov: oracle.run(oracle.HASH_EXPAND, ov[0], ov[1])
+    with ThreadPoolExecutor(T) as pool:
+        got = list(pool.map(run_part, parts))
+        ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+        for f in ("count", "sum", "min", "max"):
+            if not np.array_equal(np.concatenate([getattr(g, f) for g in got]), getattr(ref, f)):
+                raise AssertionError(f"threaded oracle differs from the serial run in {f}")
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            list(pool.map(run_part, parts))
+            reps += 1
+            t = time.perf_counter() - t0
+            if t >= budget_s or reps >= 256:
+                break
+    return {"value": reps * n / t, "unit": "elements/s", "cores": T, "kind": "oracle",
+            "sample": f"{reps} runs of 2^24 elements (regions of {L}), the serial oracle on {T} contiguous "
+                      f"parent ranges in {T} threads, results checked equal to one serial run, {t:.1f} s"}
 
 
 def main():
@@ -252,8 +320,9 @@ def main():
         offsets = torch.from_numpy(workloads.fixed_offsets(N_ELEMENTS, L).view(np.int32)).cuda()
         row = {"L": L}
         for s in strategies:
-            ms, kms, w, st = time_config(rs, torch, stream, offsets, copies, s, args.width, args.steps,
-                                         args.warmup, stats=args.occupancy)
+            ms, kt, w, st = time_config(rs, torch, stream, offsets, copies, s, args.width, args.steps,
+                                        args.warmup, stats=args.occupancy)
+            kms = kt["mean"]
             eps = N_ELEMENTS / (ms * 1e-3)
             gbs = algorithmic_bytes(N_ELEMENTS, L) / (ms * 1e-3) / 1e9
             row[names[s]] = {"ms": round(ms, 4), "kernel_ms": round(kms, 4), "elements_per_s": eps,
@@ -266,11 +335,12 @@ def main():
             print(f"[bench] L={L:5d} {names[s]:6s} w={w:4d} {ms:8.3f} ms  {eps / 1e9:7.2f} Gelem/s  {gbs:7.1f} GB/s",
                   file=sys.stderr, flush=True)
             if L == HEADLINE_L:
-                head[names[s]] = (ms, eps, gbs, w, kms)
+                head[names[s]] = (ms, eps, gbs, w, kt)
         sweep.append(row)
 
     best = max(head, key=lambda k: head[k][1])
-    ms, eps, gbs, w_best, kms = head[best]
+    ms, eps, gbs, w_best, kt_best = head[best]
+    kms = kt_best["mean"]
     # roofline of the dominant kernel: algorithmic bytes over its own mean launch duration
     kgbs = algorithmic_bytes(N_ELEMENTS, HEADLINE_L) / (kms * 1e-3) / 1e9
     probe = probe_copy(rs, torch, stream)
@@ -294,6 +364,7 @@ def main():
                    "ensemble_width": w_best, "input_copies_rotated": COPIES},
         "roofline": {"bound": "hbm", "achieved": round(kgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel_ms": round(kms, 4),
+                     "kernel_ms_median": round(kt_best["median"], 4), "kernel_ms_min": round(kt_best["min"], 4),
                      "kernel": f"rs_pipeline<HASH_EXPAND, {best}, ensemble {w_best}>",
                      "algorithmic_bytes_per_launch": algorithmic_bytes(N_ELEMENTS, HEADLINE_L)},
         "hbm_probe": probe,
@@ -306,6 +377,7 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(HEADLINE_L)
+        line["cpu_baseline_threads"] = cpu_baseline_threads(HEADLINE_L)
     print(json.dumps(line))
 
 
