@@ -208,6 +208,84 @@ def serving(rs, torch, stream, n_streams=512, rhos=(0.5, 0.8, 1.2), headline_rho
     return out
 
 
+def other_configs(rs, torch, stream, steps=5):
+    """The other workloads beside the hash/expand sweep, each at its full size, both strategies,
+    widths from the autotuner: C1 (4096 parents of 0..64 u32, mod-4 filter; latency-bound, so the
+    replay latency of one launch is reported), C3 (1 GiB of text lines: words and longest word per
+    line; elements are bytes) and C4 (2^24 vertices, 2^28 weighted edges, per-vertex threshold
+    filter; count and sum)."""
+    import workloads
+
+    def dev(a):
+        a = np.ascontiguousarray(a)
+        return torch.from_numpy(a.view(np.int32) if a.dtype == np.uint32 else a).cuda()
+
+    def kernel_rate(kind, offsets, elements, n_bytes_alg, lengths=None, parent_param=None, fields=None, param=None):
+        res = {}
+        for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+            kw = {} if param is None else {"param": param}
+            with rs.Pipeline(kind, strategy=s, ensemble_width=0, agg_fields=fields, flags=rs.RS_TIME_KERNEL,
+                             **kw) as p:
+                p.set_stream(stream.cuda_stream)
+                sid = p.push(offsets, elements, lengths=lengths, parent_param=parent_param,
+                             n_elements=int(elements.numel()))
+                p.run()
+                w = int(p.stats(sid).ensemble_width)
+                for _ in range(2):
+                    p.run_again(rs.RS_RUN_ASYNC)
+                torch.cuda.synchronize()
+                p.kernel_times()
+                for _ in range(steps):
+                    p.run_again(rs.RS_RUN_ASYNC)
+                kt = p.kernel_times()
+            ms = float(np.median(kt))
+            n = int(elements.numel())
+            res[name] = {"ensemble_width": w, "kernel_ms_median": round(ms, 4),
+                         "elements_per_s": n / (ms * 1e-3), "GB_per_s": round(n_bytes_alg / (ms * 1e-3) / 1e9, 1)}
+        return res
+
+    out = {}
+    # C1: replay latency of one launch (graph replay), events around each replay
+    offsets, vals = workloads.modfilter_workload(seed=1)
+    o, v = dev(offsets), dev(vals)
+    c1 = {}
+    for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+        with rs.Pipeline(rs.RS_MODFILTER, strategy=s, ensemble_width=0, agg_fields=rs.RS_COUNT | rs.RS_SUM,
+                         param=(4, 0, 0, 0)) as p:
+            p.set_stream(stream.cuda_stream)
+            sid = p.push(o, v, n_elements=len(vals))
+            p.run()
+            w = int(p.stats(sid).ensemble_width)
+            lat = []
+            for r in range(23):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                p.run_again(rs.RS_RUN_ASYNC)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r >= 3:
+                    lat.append(e0.elapsed_time(e1) * 1e3)
+        c1[name] = {"ensemble_width": w, "replay_us_median": round(float(np.median(lat)), 1),
+                    "replay_us_min": round(float(np.min(lat)), 1)}
+    out["C1_modfilter_4096_parents"] = {"n_elements": len(vals), "n_parents": len(offsets) - 1, **c1}
+    # C3: 1 GiB of text
+    text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 30)
+    R = len(starts)
+    out["C3_text_1GiB"] = {"n_elements": len(text), "n_parents": R, **kernel_rate(
+        rs.RS_TEXT_WORDS, dev(starts), dev(text), len(text) + 8 * R + 8 * R, lengths=dev(lengths),
+        fields=rs.RS_COUNT | rs.RS_MAX)}
+    del text, starts, lengths
+    # C4: 2^24 vertices, 2^28 edges
+    offsets, w, thr, _ = workloads.graph_workload(seed=4)
+    R = len(offsets) - 1
+    N = len(w)
+    out["C4_graph_2p28_edges"] = {"n_elements": N, "n_parents": R, **kernel_rate(
+        rs.RS_GRAPH_THRESH, dev(offsets), dev(w), 4 * N + 4 * (R + 1) + 4 * R + 12 * R, parent_param=dev(thr),
+        fields=rs.RS_COUNT | rs.RS_SUM)}
+    return out
+
+
 def host_info():
     """CPU model and thread counts of the machine the bench runs on."""
     model = ""
@@ -292,6 +370,7 @@ def main():
     ap.add_argument("--strategy", choices=["tag", "signal", "both"], default="both")
     ap.add_argument("--occupancy", action="store_true", help="collect per-node firing statistics in the sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the 512-stream batching/serving leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the C1/C3/C4 workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
@@ -370,6 +449,11 @@ def main():
         "hbm_probe": probe,
         "sweep": sweep,
     }
+    if not args.headline_only and not args.no_configs:
+        t_c = time.perf_counter()
+        line["configs"] = other_configs(rs, torch, stream)
+        print(f"[bench] other configs {time.perf_counter() - t_c:.1f} s: {json.dumps(line['configs'])}",
+              file=sys.stderr, flush=True)
     if not args.no_serving and not args.headline_only:
         t_s = time.perf_counter()
         line["serving"] = serving(rs, torch, stream)
