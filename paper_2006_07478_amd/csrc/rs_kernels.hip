@@ -223,18 +223,48 @@ __device__ __forceinline__ void acc_add(Acc &a, uint32_t y, bool act) {
     a.mx = a.mx > hi ? a.mx : hi;
 }
 
-// Wave reduction of per-lane accumulators; every lane gets the result.
+// x moved across lanes by one DPP control; lanes with no source in the pattern (or in rows
+// outside row_mask) get id instead.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_or(uint32_t id, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, CTRL, ROW_MASK, 0xF, false);
+}
+
+// One step of the lane-63 reduction for all four fields.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void acc_dpp_step(Acc &a) {
+    const uint32_t c = dpp_or<CTRL, ROW_MASK>(0u, a.cnt);
+    const uint32_t lo = dpp_or<CTRL, ROW_MASK>(0u, (uint32_t)a.sum);
+    const uint32_t hi = dpp_or<CTRL, ROW_MASK>(0u, (uint32_t)(a.sum >> 32));
+    const uint32_t mn = dpp_or<CTRL, ROW_MASK>(0xFFFFFFFFu, a.mn);
+    const uint32_t mx = dpp_or<CTRL, ROW_MASK>(0u, a.mx);
+    a.cnt += c;
+    a.sum += ((unsigned long long)hi << 32) | lo;
+    a.mn = a.mn < mn ? a.mn : mn;
+    a.mx = a.mx > mx ? a.mx : mx;
+}
+
+// Wave reduction of per-lane accumulators into wave-uniform values, with DPP moves only (no LDS
+// crossbar): an inclusive scan within each row of 16 lanes (shifts by 1, 2, 4, 8), then the
+// row totals carried across rows by the row broadcasts of lane 15 and lane 31; lane 63 ends
+// with the total, which is read into scalar registers.  Must run with every lane active.
 __device__ __forceinline__ Acc wave_reduce(Acc a) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        a.cnt += __shfl_xor(a.cnt, o, 64);
-        a.sum += __shfl_xor(a.sum, o, 64);
-        const uint32_t m0 = __shfl_xor(a.mn, o, 64);
-        const uint32_t m1 = __shfl_xor(a.mx, o, 64);
-        a.mn = a.mn < m0 ? a.mn : m0;
-        a.mx = a.mx > m1 ? a.mx : m1;
-    }
-    return a;
+    acc_dpp_step<0x111, 0xF>(a);   // row_shr:1
+    acc_dpp_step<0x112, 0xF>(a);   // row_shr:2
+    acc_dpp_step<0x114, 0xF>(a);   // row_shr:4
+    acc_dpp_step<0x118, 0xF>(a);   // row_shr:8
+    acc_dpp_step<0x142, 0xA>(a);   // row_bcast:15 into rows 1 and 3
+    acc_dpp_step<0x143, 0xC>(a);   // row_bcast:31 into rows 2 and 3
+    Acc r;
+    // readlane yields an int: each half goes through uint32_t so the low half is not
+    // sign-extended into the high one
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)a.sum, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(a.sum >> 32), 63);
+    r.cnt = (uint32_t)__builtin_amdgcn_readlane(a.cnt, 63);
+    r.sum = ((unsigned long long)hi << 32) | lo;
+    r.mn = (uint32_t)__builtin_amdgcn_readlane(a.mn, 63);
+    r.mx = (uint32_t)__builtin_amdgcn_readlane(a.mx, 63);
+    return r;
 }
 
 // ---------------------------------------------------------------- geometry
