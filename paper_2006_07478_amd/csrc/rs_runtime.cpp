@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <vector>
@@ -64,26 +65,101 @@ constexpr uint64_t kEpochCycle = 0xFFFFFFull;
 
 enum StreamState { S_PUSHED = 0, S_LAUNCHED = 1, S_DONE = 2 };
 
+// Device blocks are recycled through a process-wide cache by size class instead of being given
+// back with hipFree, which waits for the whole device: a serving loop that releases a finished
+// stream would otherwise stall behind every launch still running.  Classes are 4 KiB, then four
+// steps per power of two (at most 25% rounding).  The cache is emptied when the last pipeline is
+// destroyed, and before an allocation that fails is retried.
+class BlockCache {
+  public:
+    static size_t class_of(size_t n) {
+        if (n <= 4096) return 4096;
+        size_t top = 4096;
+        while (top < n) top <<= 1;
+        const size_t q = top >> 3;   // quarter steps between top/2 and top
+        size_t c = top >> 1;
+        while (c < n) c += q;
+        return c;
+    }
+    int get(size_t n, void **out, size_t *cls, int *dev) {
+        HIP_OR(hipGetDevice(dev), RS_EDEVICE);
+        *cls = class_of(n);
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            auto it = free_.find({*dev, *cls});
+            if (it != free_.end() && !it->second.empty()) {
+                *out = it->second.back();
+                it->second.pop_back();
+                cached_ -= *cls;
+                return RS_OK;
+            }
+        }
+        hipError_t e = hipMalloc(out, *cls);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            e = hipMalloc(out, *cls);
+        }
+        if (e != hipSuccess) {
+            *out = nullptr;
+            return fail(RS_ENOMEM, "hipMalloc(%zu): %s", *cls, hipGetErrorString(e));
+        }
+        return RS_OK;
+    }
+    void put(void *p, size_t cls, int dev) {
+        std::lock_guard<std::mutex> g(mu_);
+        free_[{dev, cls}].push_back(p);
+        cached_ += cls;
+    }
+    // Returns every cached block with hipFree (callers know no kernel uses them).
+    void trim() {
+        std::map<std::pair<int, size_t>, std::vector<void *>> all;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            all.swap(free_);
+            cached_ = 0;
+        }
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        for (auto &kv : all) {
+            (void)hipSetDevice(kv.first.first);
+            for (void *p : kv.second) (void)hipFree(p);
+        }
+        (void)hipSetDevice(cur);
+    }
+
+  private:
+    std::mutex mu_;
+    std::map<std::pair<int, size_t>, std::vector<void *>> free_;
+    size_t cached_ = 0;
+};
+
+BlockCache &block_cache() {
+    static BlockCache *c = new BlockCache;   // outlives static destructors that might still free
+    return *c;
+}
+int g_live_pipelines = 0;
+std::mutex g_live_mu;
+
 struct DevBuf {
     void *p = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;   // bytes asked for
+    size_t cls = 0;     // bytes held (the size class)
+    int dev = 0;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { reset(); }
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) block_cache().put(p, cls, dev);
         p = nullptr;
-        bytes = 0;
+        bytes = cls = 0;
     }
     int alloc(size_t n) {
         reset();
         if (n == 0) n = 16;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return fail(RS_ENOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
-        }
+        const int rc = block_cache().get(n, &p, &cls, &dev);
+        if (rc) return rc;
         bytes = n;
         return RS_OK;
     }
@@ -119,6 +195,9 @@ struct Batch {
     hipGraphExec_t graph = nullptr;
     hipEvent_t done = nullptr;
     ~Batch() {
+        // the table and control block go back to the block cache after this body: the last
+        // launch must have finished reading them
+        if (done && launches) (void)hipEventSynchronize(done);
         if (graph) (void)hipGraphExecDestroy(graph);
         if (done) (void)hipEventDestroy(done);
     }
@@ -131,6 +210,7 @@ struct rs_pipeline {
     int device = 0;
     int n_cu = 0;
     hipStream_t own[2] = {nullptr, nullptr};
+    hipStream_t copy = nullptr;    // host-to-device copies of pushed streams, apart from the launch lanes
     hipStream_t user_stream = nullptr;
     bool one_lane = false;         // every batch on the first lane (the per-stream baseline)
     uint32_t width = 0, strategy = 0;
@@ -530,6 +610,11 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     HIP_OR(hipGetDeviceProperties(&prop, p->device), RS_EDEVICE);
     p->n_cu = prop.multiProcessorCount;
     for (auto &h : p->own) HIP_OR(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), RS_EDEVICE);
+    HIP_OR(hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking), RS_EDEVICE);
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        ++g_live_pipelines;
+    }
     p->width = d->ensemble_width;
     p->strategy = d->strategy == RS_AUTO ? RS_TAG : d->strategy;
     p->configured = d->ensemble_width != 0 && d->strategy != RS_AUTO;
@@ -606,7 +691,8 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
         return fail(RS_EBUDGET, "stream needs %llu bytes, budget is %llu", (unsigned long long)st->footprint,
                     (unsigned long long)p->d.hbm_budget_bytes);
 
-    hipStream_t hs = lane_of(p, 0);
+    // copies go on the pipeline's copy stream: a push does not wait for running launches
+    hipStream_t hs = p->copy;
     if (s->mem == RS_MEM_HOST) {
         if ((rc = st->own_elements.alloc(s->n_elements * eb + 16))) return rc;
         if (s->n_elements)
@@ -629,8 +715,6 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
                 st->pparam = (const uint32_t *)st->own_pparam.p;
             }
         }
-        // the caller may reuse its host arrays as soon as this returns
-        HIP_OR(hipStreamSynchronize(hs), RS_EDEVICE);
     } else {
         st->elements = s->elements;
         st->offsets = s->offsets;
@@ -643,7 +727,10 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
     if (p->d.agg_fields & RS_MIN && (rc = st->min.alloc(4 * P))) return rc;
     if (p->d.agg_fields & RS_MAX && (rc = st->max.alloc(4 * P))) return rc;
     if ((rc = st->stats.alloc(8 * rs::ST_WORDS))) return rc;
-    HIP_OR(hipMemset(st->stats.p, 0, 8 * rs::ST_WORDS), RS_EDEVICE);
+    HIP_OR(hipMemsetAsync(st->stats.p, 0, 8 * rs::ST_WORDS, hs), RS_EDEVICE);
+    // the copies and the clear have landed before any launch reads them, and the caller may
+    // reuse its host arrays as soon as this returns
+    HIP_OR(hipStreamSynchronize(hs), RS_EDEVICE);
     if (p->d.emit_outputs && (rc = st->out.alloc(4 * st->out_cap + 16))) return rc;
 
     st->id = p->next_id++;
@@ -1004,10 +1091,18 @@ RS_API int pipeline_destroy(rs_pipeline *p) {
             (void)hipEventDestroy(ev.first);
             (void)hipEventDestroy(ev.second);
         }
+    if (p->copy) (void)hipStreamSynchronize(p->copy);
     p->batches.clear();
     p->streams.clear();
     for (auto &h : p->own)
         if (h) (void)hipStreamDestroy(h);
+    if (p->copy) (void)hipStreamDestroy(p->copy);
     delete p;
+    bool last = false;
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        last = --g_live_pipelines == 0;
+    }
+    if (last) block_cache().trim();   // nothing can use a cached block any more
     return RS_OK;
 }
