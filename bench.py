@@ -101,6 +101,51 @@ def time_config(rs, torch, stream, offsets, copies, strategy, width, steps, warm
     return ms, kernel_ms, chosen, st
 
 
+def occupancy_pass(rs, torch, stream, offsets, vals, strategy, width, L):
+    """One launch with device statistics (kept out of the timed launches): lane occupancy and share
+    of full firings per node; for signals beside the closed form L/(w ceil(L/w)) of the
+    enumerating node (§5)."""
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=width, flags=rs.RS_COLLECT_STATS) as p:
+        p.set_stream(stream.cuda_stream)
+        sid = p.push(offsets, vals, n_elements=N_ELEMENTS)
+        p.run()
+        st = p.stats(sid)
+    occ = lambda k: round(st.items[k] / max(1, st.firings[k] * width), 4)
+    full = lambda k: round(st.full[k] / max(1, st.firings[k]), 4)
+    out = {"enum_occupancy": occ(0), "enum_full_frac": full(0), "expand_occupancy": occ(1),
+           "agg_occupancy": occ(2), "agg_full_frac": full(2)}
+    if strategy == rs.RS_SIGNAL:
+        out["enum_occupancy_closed_form"] = round(L / (width * -(-L // width)), 4)
+    return out
+
+
+def output_stream_rate(rs, torch, stream, vals, L, steps=5):
+    """The ordered output stream (emit_outputs) at the headline size, both strategies: the
+    pipeline kernel's median, and algorithmic bytes with 4 B per output item added."""
+    offsets = torch.from_numpy(__import__("workloads").fixed_offsets(N_ELEMENTS, L).view(np.int32)).cuda()
+    res = {}
+    for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=s, ensemble_width=0, emit_outputs=True,
+                         flags=rs.RS_TIME_KERNEL) as p:
+            p.set_stream(stream.cuda_stream)
+            sid = p.push(offsets, vals, n_elements=N_ELEMENTS)
+            p.run()
+            st = p.stats(sid)
+            for _ in range(2):
+                p.run_again(rs.RS_RUN_ASYNC)
+            torch.cuda.synchronize()
+            p.kernel_times()
+            for _ in range(steps):
+                p.run_again(rs.RS_RUN_ASYNC)
+            kt = p.kernel_times()
+        ms = float(np.median(kt))
+        nbytes = algorithmic_bytes(N_ELEMENTS, L) + 4 * int(st.n_outputs)
+        res[name] = {"ensemble_width": int(st.ensemble_width), "n_outputs": int(st.n_outputs),
+                     "kernel_ms_median": round(ms, 4), "elements_per_s": N_ELEMENTS / (ms * 1e-3),
+                     "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    return res
+
+
 def probe_copy(rs, torch, stream, nbytes=1 << 30, reps=10):
     """The library's plain 1 GiB copy: achievable-bandwidth reference and counter calibration."""
     src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -377,7 +422,7 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="time only L = 4096 (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", choices=["tag", "signal", "both"], default="both")
-    ap.add_argument("--occupancy", action="store_true", help="collect per-node firing statistics in the sweep")
+    ap.add_argument("--no-occupancy", action="store_true", help="skip the per-node statistics pass of the sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the 512-stream batching/serving leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1/C3/C4 workloads")
     args = ap.parse_args()
@@ -408,18 +453,15 @@ def main():
         offsets = torch.from_numpy(workloads.fixed_offsets(N_ELEMENTS, L).view(np.int32)).cuda()
         row = {"L": L}
         for s in strategies:
-            ms, kt, w, st = time_config(rs, torch, stream, offsets, copies, s, args.width, args.steps,
-                                        args.warmup, stats=args.occupancy)
+            ms, kt, w, _ = time_config(rs, torch, stream, offsets, copies, s, args.width, args.steps,
+                                       args.warmup)
             kms = kt["mean"]
             eps = N_ELEMENTS / (ms * 1e-3)
             gbs = algorithmic_bytes(N_ELEMENTS, L) / (ms * 1e-3) / 1e9
             row[names[s]] = {"ms": round(ms, 4), "kernel_ms": round(kms, 4), "elements_per_s": eps,
                              "GB_per_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "ensemble_width": w}
-            if st is not None:
-                # enumerating node: mean ensemble fill and share of full firings (the §5 statistic)
-                row[names[s]]["enum_fill"] = round(st.items[0] / max(1, st.firings[0] * w), 4)
-                row[names[s]]["enum_full_frac"] = round(st.full[0] / max(1, st.firings[0]), 4)
-                row[names[s]]["agg_full_frac"] = round(st.full[2] / max(1, st.firings[2]), 4)
+            if not args.no_occupancy and not args.headline_only:   # headline-only: the profiled command
+                row[names[s]].update(occupancy_pass(rs, torch, stream, offsets, copies[0], s, w, L))
             print(f"[bench] L={L:5d} {names[s]:6s} w={w:4d} {ms:8.3f} ms  {eps / 1e9:7.2f} Gelem/s  {gbs:7.1f} GB/s",
                   file=sys.stderr, flush=True)
             if L == HEADLINE_L:
@@ -458,6 +500,9 @@ def main():
         "hbm_probe": probe,
         "sweep": sweep,
     }
+    if not args.headline_only:
+        line["output_stream"] = output_stream_rate(rs, torch, stream, copies[0], HEADLINE_L)
+        print(f"[bench] output stream: {json.dumps(line['output_stream'])}", file=sys.stderr, flush=True)
     if not args.headline_only and not args.no_configs:
         t_c = time.perf_counter()
         line["configs"] = other_configs(rs, torch, stream)
