@@ -114,9 +114,40 @@ def occupancy_pass(rs, torch, stream, offsets, vals, strategy, width, L):
     full = lambda k: round(st.full[k] / max(1, st.firings[k]), 4)
     out = {"enum_occupancy": occ(0), "enum_full_frac": full(0), "expand_occupancy": occ(1),
            "agg_occupancy": occ(2), "agg_full_frac": full(2)}
-    if strategy == rs.RS_SIGNAL:
+    if strategy == rs.RS_SIGNAL and L > 0:
         out["enum_occupancy_closed_form"] = round(L / (width * -(-L // width)), 4)
     return out
+
+
+VARIABLE_MAX = [2, 8, 32, 128, 512, 2048, 8192]
+
+
+def variable_sweep(rs, torch, stream, copies, steps, warmup, width=0):
+    """Region sizes uniform in [0, max] over 2^26 elements, both strategies (the paper's second
+    synthetic experiment): elements/s and algorithmic GB/s from the pipeline kernel's mean, and
+    the enumerating node's lane occupancy beside its closed form sum(n) / (w sum(ceil(n/w)))."""
+    import workloads
+    rows = []
+    for mx in VARIABLE_MAX:
+        offs_h = workloads.variable_offsets(2, N_ELEMENTS, mx)
+        sizes = np.diff(offs_h.astype(np.int64))
+        R = len(sizes)
+        offsets = torch.from_numpy(offs_h.view(np.int32)).cuda()
+        row = {"max": mx, "regions": R}
+        for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+            ms, kt, w, _ = time_config(rs, torch, stream, offsets, copies, s, width, steps, warmup)
+            kms = kt["mean"]
+            nbytes = 4 * N_ELEMENTS + 4 * (R + 1) + 20 * R
+            row[name] = {"ensemble_width": w, "ms": round(ms, 4), "kernel_ms": round(kms, 4),
+                         "elements_per_s": N_ELEMENTS / (kms * 1e-3), "GB_per_s": round(nbytes / (kms * 1e-3) / 1e9, 1)}
+            occ = occupancy_pass(rs, torch, stream, offsets, copies[0], s, w, 0)
+            row[name]["enum_occupancy"] = occ["enum_occupancy"]
+            if s == rs.RS_SIGNAL:
+                row[name]["enum_occupancy_closed_form"] = round(float(sizes.sum()) / (w * float(np.sum(-(-sizes // w)))), 4)
+            print(f"[bench] variable max={mx:5d} {name:6s} w={w:4d} kernel {kms:8.3f} ms  "
+                  f"{N_ELEMENTS / (kms * 1e-3) / 1e9:7.2f} Gelem/s", file=sys.stderr, flush=True)
+        rows.append(row)
+    return rows
 
 
 def output_stream_rate(rs, torch, stream, vals, L, steps=5):
@@ -425,6 +456,7 @@ def main():
     ap.add_argument("--no-occupancy", action="store_true", help="skip the per-node statistics pass of the sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the 512-stream batching/serving leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1/C3/C4 workloads")
+    ap.add_argument("--no-variable", action="store_true", help="skip the variable-size sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
@@ -500,6 +532,8 @@ def main():
         "hbm_probe": probe,
         "sweep": sweep,
     }
+    if not args.headline_only and not args.no_variable:
+        line["variable_sweep"] = variable_sweep(rs, torch, stream, copies, args.steps, args.warmup, args.width)
     if not args.headline_only:
         line["output_stream"] = output_stream_rate(rs, torch, stream, copies[0], HEADLINE_L)
         print(f"[bench] output stream: {json.dumps(line['output_stream'])}", file=sys.stderr, flush=True)

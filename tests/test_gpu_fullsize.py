@@ -66,6 +66,19 @@ def test_hash_expand_2p26(L):
         check(got, ref, ("count", "sum", "min", "max"), f"2^26 L={L} {SNAME[s]}")
 
 
+@pytest.mark.parametrize("mx", [16, 2048])
+def test_variable_sizes_2p26(mx):
+    """The variable-size sweep at its full size: region sizes uniform in [0, max]."""
+    n = 1 << 26
+    offsets = workloads.variable_offsets(13, n, mx)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    for s in STRATS:
+        say("2^26 variable sizes max", mx, SNAME[s])
+        got, st = run_dev(rs.RS_HASH_EXPAND, s, offsets, vals)
+        check(got, ref, ("count", "sum", "min", "max"), f"2^26 variable max={mx} {SNAME[s]}")
+
+
 def test_text_1gib():
     text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 30)
     say("text 1 GiB:", len(starts), "lines")

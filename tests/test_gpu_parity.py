@@ -240,6 +240,27 @@ def test_signal_occupancy_matches_closed_form():
         assert st_t.items[0] == n and st_t.signals[0] == 0
 
 
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("mx", [1, 7, 64, 300, 5000])
+def test_variable_size_regions(strategy, mx):
+    """Region sizes uniform in [0, max] (the variable-size sweep): records equal the oracle's,
+    and for signals the enumerating node fires ceil(n_p/w) times per region, full floor(n_p/w)."""
+    say("variable sizes", SNAME[strategy], mx)
+    n = 300007
+    offsets = workloads.variable_offsets(11, n, mx)
+    vals = workloads.hash_values(12, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    sizes = np.diff(offsets.astype(np.int64))
+    for w in (64, 256):
+        got, st = run_one(rs.RS_HASH_EXPAND, strategy, w, offsets, vals, flags=rs.RS_COLLECT_STATS)
+        check(got, ref, where=f"variable max={mx} {SNAME[strategy]} w={w}")
+        assert st.items[0] == n
+        if strategy == rs.RS_SIGNAL:
+            assert st.firings[0] == int(np.sum(-(-sizes // w)))
+            assert st.full[0] == int(np.sum(sizes // w))
+            assert st.signals[0] == len(sizes)
+
+
 # ---- ordered output stream ----
 
 def run_outputs(kind, strategy, width, offsets, elements, lengths=None, parent_param=None):

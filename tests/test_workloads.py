@@ -72,3 +72,22 @@ def test_serving_shapes_and_streams():
     assert len(vals) == 5000
     t = W.arrivals(6, 100, 50.0)
     assert (np.diff(t) > 0).all() and abs(t[-1] / 100 - 1 / 50.0) < 0.01
+
+
+def test_variable_offsets_cover_exactly_n():
+    """Variable-size sweep regions: sizes in [0, max], the whole stream covered exactly once,
+    only the last region cut short, and the same draw for the same seed."""
+    for mx, n in ((1, 5000), (7, 100003), (64, 100003), (4096, 1 << 20)):
+        o = W.variable_offsets(3, n, mx).astype(np.int64)
+        d = np.diff(o)
+        assert o[0] == 0 and o[-1] == n
+        assert d.min() >= 0 and d.max() <= mx
+        assert np.array_equal(o, W.variable_offsets(3, n, mx).astype(np.int64))
+        # the uncut sizes come from the same generator as uniform_offsets
+        full = np.diff(W.uniform_offsets(3, len(d), mx).astype(np.int64))
+        assert np.array_equal(d[:-1], full[:-1]) and d[-1] <= full[-1]
+        # sizes look uniform on [0, mx]: the mean of many draws is near mx / 2
+        if len(d) > 1000:
+            assert abs(d[:-1].mean() - mx / 2) < 0.05 * mx + 0.05
+    e = W.variable_offsets(3, 1000, 0)
+    assert len(e) == 4097 and not e.any()

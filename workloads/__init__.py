@@ -113,6 +113,27 @@ def uniform_offsets(seed, n_parents, max_size):
     return sizes_to_offsets(sizes)
 
 
+def variable_offsets(seed, n, max_size):
+    """Regions with sizes uniform in [0, max_size] that cover exactly n elements: sizes are
+    drawn until their sum reaches n, and the last region is cut to fit (the variable-size
+    sweep)."""
+    if max_size == 0:
+        return np.zeros(4097, np.uint32)   # 4096 empty regions: nothing can cover n
+    mean = max_size / 2.0
+    P = int(np.ceil(n / mean * 1.1)) + 64
+    while True:
+        sizes = np.zeros(P, np.uint32)
+        lib().gen_uniform_sizes(seed, max_size, P, sizes.ctypes.data)
+        ends = np.cumsum(sizes, dtype=np.int64)
+        if ends[-1] >= n:
+            break
+        P *= 2
+    last = int(np.searchsorted(ends, n))     # first region whose end reaches n
+    offsets = np.zeros(last + 2, np.uint32)
+    offsets[1:] = np.minimum(ends[:last + 1], n)
+    return offsets
+
+
 # ---- line-structured text ----
 
 def text_workload(seed=3, total_bytes=1 << 30, mean_len=80.0, max_len=65536, space_per_65536=11796):
