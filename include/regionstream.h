@@ -50,9 +50,13 @@ enum rs_status {
 };
 
 /* Boundary transport.  RS_SIGNAL: end-of-region signals on a finite signal queue beside each
- * data queue, delivered precisely with credit (§3.1-§3.3);
- * RS_TAG: a region tag on every item (§5); RS_AUTO: the autotuner chooses. */
-enum rs_strategy { RS_TAG = 0, RS_SIGNAL = 1, RS_AUTO = 2 };
+ * data queue, delivered precisely with credit (§3.1-§3.3), so no ensemble spans a boundary;
+ * RS_TAG: a region tag on every item (§5); RS_AUTO: the autotuner chooses;
+ * RS_SIGNAL_LANES: the lane-resolved signals the paper proposes as future work (§6): the same
+ * signal queues, but an ensemble may span boundaries and every node computes each lane's
+ * region from the pending signals' positions instead of storing it with the items.  Offered for
+ * u32 kinds (not RS_TEXT_WORDS) at ensemble widths 64, 128 and 256. */
+enum rs_strategy { RS_TAG = 0, RS_SIGNAL = 1, RS_AUTO = 2, RS_SIGNAL_LANES = 3 };
 
 /* Stage kinds (hand-written HIP stages; there is no user device code).
  *   RS_MODFILTER    u32 elements; keep x mod param[0] == param[1] (param[0] 0 means 4); k = 1.

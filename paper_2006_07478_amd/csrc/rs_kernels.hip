@@ -267,6 +267,21 @@ __device__ __forceinline__ Acc wave_reduce(Acc a) {
     return r;
 }
 
+// Set bits among ensemble indices [0, rel) of the per-round masks m (index k*64 + lane is bit
+// lane of m[k]); rel is per lane, at most 64*V.
+template <int V>
+__device__ __forceinline__ uint32_t bits_below(const uint64_t (&m)[V], uint32_t rel) {
+    uint32_t n = 0;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const uint32_t lo = (uint32_t)k * 64u;
+        const uint32_t r = rel > lo ? min(rel - lo, 64u) : 0u;
+        const uint64_t low = r >= 64u ? ~0ull : ((1ull << r) - 1ull);
+        n += (uint32_t)__popcll(m[k] & low);
+    }
+    return n;
+}
+
 // ---------------------------------------------------------------- geometry
 
 template <int V, bool HAS_E, uint32_t KE>
@@ -351,6 +366,12 @@ struct ClaimRegs {
 template <int KIND, int STRAT, int V>
 __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     constexpr bool TAG = (STRAT == RS_TAG);
+    // lane-resolved signals: ensembles span region boundaries, the boundaries travel on the
+    // signal queues only, and every node computes each lane's region from the pending signals
+    constexpr bool LANES = (STRAT == RS_SIGNAL_LANES);
+    // the enumerating node walks consecutive positions and the aggregating node resolves regions
+    // per lane (tags, or lane-resolved signals); plain signals cap every ensemble at its region
+    constexpr bool WALK = TAG || LANES;
     constexpr bool HAS_E = (KIND == RS_HASH_EXPAND || KIND == RS_TEXT_WORDS);
     constexpr bool BYTES = (KIND == RS_TEXT_WORDS);
     constexpr bool CTXP = (KIND == RS_GRAPH_THRESH);
@@ -358,6 +379,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     using G = Geo<V, HAS_E, KE>;
     constexpr uint32_t EW = G::EW, D1 = G::D1, D2 = G::D2, SQ = G::SQ, R = G::R;
     constexpr uint32_t DA = HAS_E ? D2 : D1;   // the aggregating node's input queue
+    static_assert(!LANES || (KIND != RS_TEXT_WORDS && V <= 4), "lane-resolved signals: u32 kinds, w <= 256");
 
     // data queues, each followed by 64 spill slots (one per lane) for dropped items
     __shared__ uint32_t q1v[D1 + 64];
@@ -552,7 +574,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             order();
             vbeg = 0;
             vend = carry;
-            if constexpr (TAG) {   // lines are enumerated over the claim's byte address range
+            if constexpr (WALK) {   // lines are enumerated over the claim's byte address range
                 vbeg = nb ? uni(SX[0]) : 0u;
                 vend = nb ? uni(SX[nb - 1] + (VT[nb] - VT[nb - 1])) : 0u;
             }
@@ -663,7 +685,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     kp = h & 1u;
                     aux = (h >> 1) & 3u;
                 } else {
-                    kp = x < (TAG ? CX[j] : thr);
+                    kp = x < (WALK ? CX[j] : thr);
                 }
                 return act && kp;
             } else {
@@ -686,27 +708,27 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         unsigned long long out_rank = 0;
         if (a.emit_outputs) {
             uint32_t fpos = vbeg, fj = 0, jlo = 0;
-            bool fdone = TAG ? (vbeg >= vend) : (nb == 0);
+            bool fdone = WALK ? (vbeg >= vend) : (nb == 0);
             unsigned long long n_out = 0;
             while (!fdone) {
-                const uint32_t rend = TAG ? vend : uni(VT[fj + 1]);
+                const uint32_t rend = WALK ? vend : uni(VT[fj + 1]);
                 const uint32_t e = min(EW, rend - fpos);
                 if (e) {
                     const uint32_t ls = BYTES ? uni(SX[fj]) : 0u, lv = BYTES ? uni(VT[fj]) : 0u;
-                    const uint32_t thr = (CTXP && !TAG) ? uni(CX[fj]) : 0u;
+                    const uint32_t thr = (CTXP && !WALK) ? uni(CX[fj]) : 0u;
                     uint32_t reg[V], x[V];
-                    if constexpr (TAG) f_regions(BoolC<false>{}, fpos, e, jlo, false, reg);
+                    if constexpr (WALK) f_regions(BoolC<false>{}, fpos, e, jlo, false, reg);
                     if constexpr (!BYTES) load_ens(fpos, e, x);
 #pragma unroll
                     for (int k = 0; k < V; ++k) {
                         const uint32_t i = (uint32_t)k * 64u + t;
                         uint32_t item, aux;
-                        const uint32_t j = TAG ? reg[k] : fj;
+                        const uint32_t j = WALK ? reg[k] : fj;
                         const bool keep = f_item(i, i < e, fpos, BYTES ? 0u : x[k], j, thr, ls, lv, item, aux);
                         const uint32_t nout = keep ? (KIND == RS_HASH_EXPAND ? aux : 1u) : 0u;
                         n_out += (uint32_t)__popcll(__ballot(nout & 1u)) + 2u * (uint32_t)__popcll(__ballot(nout & 2u));
                     }
-                    if constexpr (TAG) {
+                    if constexpr (WALK) {
                         const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
 #pragma unroll
                         for (int k = 0; k < V; ++k)
@@ -714,7 +736,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     }
                 }
                 fpos += e;
-                if constexpr (TAG) {
+                if constexpr (WALK) {
                     fdone = (fpos == vend);
                 } else if (fpos == rend) {
                     ++fj;
@@ -758,16 +780,20 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         uint32_t rend = 0, ls = 0, lv = 0;                  // current region's end, line address, line position
         // tag strategy: start of region jlo + 1 (every position below it lies in region jlo or before)
         uint32_t jnext = 0xFFFFFFFFu;
-        if constexpr (TAG) {
+        if constexpr (WALK) {
             if (nb > 1u) jnext = uni((BYTES ? SX : VT)[1]);
         }
-        if constexpr (!TAG) {
+        if constexpr (!WALK) {
             if (nb) {
                 rend = uni(VT[1]);
                 if constexpr (BYTES) ls = uni(SX[0]);
             }
         }
-        bool fdone = TAG ? (vbeg >= vend) : (nb == 0);
+        // lane-resolved signals: the next region whose end the enumerating node has not signalled
+        uint32_t jb = 0;
+        // lane-resolved signals finish once every position is enumerated and every region's end
+        // is signalled (empty regions included)
+        bool fdone = LANES ? (vbeg >= vend && nb == 0) : TAG ? (vbeg >= vend) : (nb == 0);
         uint32_t ej = 0;                      // signal strategy: region E is in
         uint32_t ja = 0, a_items = 0;         // signal strategy: region A closes next, items it has taken
         Acc acc;
@@ -822,9 +848,24 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 y[k] = qv[pos];
                 if constexpr (TAG) tg[k] = qt[pos]; else tg[k] = 0u;
             }
+            if constexpr (LANES) {
+                // each lane's region: the head region ja plus the pending signals at or before its
+                // item (a signal at queue position p ends a region just before the item at p)
+                const uint32_t sqa = HAS_E ? sq2 : sq1, sha = HAS_E ? sh2 : sh1;
+                const uint32_t pend = (HAS_E ? st2 : st1) - sha, hq = HAS_E ? h2 : h1;
+                const uint32_t ns =
+                    (uint32_t)__popcll(__ballot(((t - sha) & (SQ - 1u)) < pend && sqa - hq < e));
+#pragma unroll
+                for (int k = 0; k < V; ++k) tg[k] = ja;
+                for (uint32_t q = 0; q < ns; ++q) {
+                    const uint32_t p = __builtin_amdgcn_readlane(sqa, (sha + q) & (SQ - 1u)) - hq;
+#pragma unroll
+                    for (int k = 0; k < V; ++k) tg[k] += (uint32_t)k * 64u + t >= p ? 1u : 0u;
+                }
+            }
             uint32_t tf = 0, tl = 0;
-            if constexpr (TAG) {
-                // tags of the ensemble's first and last items, from the values just read
+            if constexpr (WALK) {
+                // regions of the ensemble's first and last items
                 tf = uni(tg[0]);
                 const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
 #pragma unroll
@@ -844,8 +885,8 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     if (FULL || i < e) out_items[out_rank + i] = y[k];   // serial order
                 }
             }
-            if (!TAG || tf == tl) {
-                if constexpr (TAG) {
+            if (!WALK || tf == tl) {
+                if constexpr (WALK) {
                     if (tf != utag) {   // every lane's accumulator closes together
                         flush_wave(utag);
                         utag = tf;
@@ -868,6 +909,17 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
                 flush_lane(lt);
                 utag = tl;
+            }
+            if constexpr (LANES) {
+                // the signals at or before the new head end their regions now
+                uint32_t &sha = HAS_E ? sh2 : sh1;
+                const uint32_t sqa = HAS_E ? sq2 : sq1;
+                const uint32_t pend = (HAS_E ? st2 : st1) - sha, hq = HAS_E ? h2 : h1;
+                const uint32_t nc =
+                    (uint32_t)__popcll(__ballot(((t - sha) & (SQ - 1u)) < pend && sqa - hq <= e));
+                ja += nc;
+                sha += nc;
+                stat(ST_SIGNALS + 2, nc);
             }
             if constexpr (HAS_E) {
                 h2 += e;
@@ -975,6 +1027,24 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
             };
             if (total <= room) write_rounds(BoolC<true>{}); else write_rounds(BoolC<false>{});
+            if constexpr (LANES) {
+                // the signals at or before the last item taken pass to the second signal queue,
+                // each re-based to the outputs of the items before it (the scheduler sized the
+                // ensemble so that they fit; equal positions beyond the room stay behind)
+                const uint32_t pend = st1 - sh1, free2 = SQ - (st2 - sh2);
+                const uint32_t rel = sq1 - h1;
+                const bool fw = ((t - sh1) & (SQ - 1u)) < pend && rel <= taken;
+                const uint32_t nf = min((uint32_t)__popcll(__ballot(fw)), free2);
+                const uint32_t r = fw ? rel : 0u;
+                const uint32_t np = t2 + bits_below<V>(b0, r) + 2u * bits_below<V>(b1, r);
+                // S1 entry sh1 + i becomes S2 entry st2 + i
+                const uint32_t i = (t - st2) & (SQ - 1u);
+                const uint32_t moved = (uint32_t)__shfl((int)np, (int)((sh1 + i) & (SQ - 1u)), 64);
+                sq2 = i < nf ? moved : sq2;
+                st2 += nf;
+                sh1 += nf;
+                stat(ST_SIGNALS + 1, nf);
+            }
             h1 += taken;
             t2 += made;
             t2w = qslot<D2>(t2w, made);
@@ -984,12 +1054,18 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         };
 
         // ---------------- F: the enumerating node, one firing of e items from fpos
-        auto f_node = [&](auto full, uint32_t e) {
+        // nbound (lane-resolved signals): the ends of regions jb .. jb + nbound - 1 fall in this
+        // ensemble or at its end, and their signals go out with it
+        auto f_node = [&](auto full, uint32_t e, uint32_t nbound) {
             constexpr bool FULL = decltype(full)::value;
+            // the items' own regions: for tags, and for lane-resolved signals of a kind that reads
+            // the parent's context
+            constexpr bool FREG = TAG || (LANES && CTXP);
             bool one = true;
-            if constexpr (TAG) one = jnext > fpos + e - 1u;
+            if constexpr (FREG) one = jnext > fpos + e - 1u;
             uint32_t reg[V], x[V];
-            if constexpr (TAG) {
+            uint64_t kb[V];   // kept-item masks per round (lane-resolved signals)
+            if constexpr (FREG) {
                 f_regions(full, fpos, e, jlo, one, reg);
             } else {
 #pragma unroll
@@ -1004,7 +1080,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = 0;
             }
-            const uint32_t thr = (CTXP && !TAG) ? uni(CX[fj]) : 0u;
+            const uint32_t thr = (CTXP && !WALK) ? uni(CX[fj]) : 0u;
             uint32_t run = 0;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
@@ -1012,6 +1088,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 uint32_t item, aux;
                 const bool keep = f_item(i, FULL || i < e, fpos, x[k], reg[k], thr, ls, lv, item, aux);
                 const uint64_t b = __ballot(keep);
+                kb[k] = b;
                 const uint32_t within = rank_below(b), pc = (uint32_t)__popcll(b);
                 // dropped lanes write spill slots on the banks the kept ones leave free
                 const uint32_t pos = pick(b, (t1 + run + within) & (D1 - 1u), D1 + ((t1 + run + pc + t - within) & 63u));
@@ -1020,7 +1097,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if constexpr (TAG) q1t[pos] = (uint8_t)reg[k];
                 run += pc;
             }
-            if constexpr (TAG) {
+            if constexpr (FREG) {
                 if (!one) {
                     const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
 #pragma unroll
@@ -1028,6 +1105,18 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                         if ((uint32_t)k == kl) jlo = __builtin_amdgcn_readlane(reg[k], ll);
                     jnext = jlo + 1u < nb ? uni((BYTES ? SX : VT)[jlo + 1u]) : 0xFFFFFFFFu;
                 }
+            }
+            if constexpr (LANES) {
+                // each region end's signal sits at the queue position of the first kept item after
+                // it; lane i mod 64 holds signal-queue entry i
+                const uint32_t i = (t - st1) & (SQ - 1u);
+                const bool mine = i < nbound;
+                const uint32_t rel = mine ? min(VT[min(jb + i + 1u, nb)] - fpos, e) : 0u;
+                const uint32_t p = t1 + bits_below<V>(kb, rel);
+                sq1 = mine ? p : sq1;
+                st1 += nbound;
+                jb += nbound;
+                stat(ST_SIGNALS + 0, nbound);
             }
             if constexpr (!BYTES) stage(fpos + e);   // the slot's contents are in registers
             t1 += run;
@@ -1047,7 +1136,20 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint32_t hq = HAS_E ? h2 : h1, tq = HAS_E ? t2 : t1;
                 uint32_t e = 0;
                 bool fire = false;
-                if constexpr (!TAG) {
+                if constexpr (LANES) {
+                    // signals with no item before them end their regions at once
+                    uint32_t &sh = HAS_E ? sh2 : sh1;
+                    const uint32_t pend = (HAS_E ? st2 : st1) - sh;
+                    const uint32_t nh = (uint32_t)__popcll(
+                        __ballot(((t - sh) & (SQ - 1u)) < pend && (HAS_E ? sq2 : sq1) == hq));
+                    if (nh) {
+                        ja += nh;
+                        sh += nh;
+                        stat(ST_SIGNALS + 2, nh);
+                        continue;
+                    }
+                }
+                if constexpr (!WALK) {
                     uint32_t &sh = HAS_E ? sh2 : sh1;
                     const uint32_t stq = HAS_E ? st2 : st1;
                     if (sh < stq) {
@@ -1077,7 +1179,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if (!fire) {
                     const bool up_done = HAS_E ? (fdone && h1 == t1) : fdone;
                     const uint32_t n = tq - hq;
-                    if (n >= EW || (up_done && n > 0)) {
+                    // lane-resolved signals: a full signal queue makes A fire what it has
+                    const bool sq_full = LANES && (HAS_E ? st2 - sh2 : st1 - sh1) == SQ;
+                    if (n >= EW || ((up_done || sq_full) && n > 0)) {
                         e = min(n, EW);
                         fire = true;
                     }
@@ -1094,7 +1198,31 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const bool room = D2 - (t2 - h2) >= KE;
                 uint32_t e = 0;
                 bool sig = false, pending = false;
-                if constexpr (!TAG) {
+                if constexpr (LANES) {
+                    pending = true;   // e is decided here
+                    const uint32_t pend = st1 - sh1, free2 = SQ - (st2 - sh2);
+                    // signals with no item before them pass on at once (sender rule: S2 has room)
+                    const uint32_t nh = min(
+                        (uint32_t)__popcll(__ballot(((t - sh1) & (SQ - 1u)) < pend && sq1 == h1)), free2);
+                    if (nh) {
+                        const uint32_t i = (t - st2) & (SQ - 1u);
+                        sq2 = i < nh ? t2 : sq2;
+                        st2 += nh;
+                        sh1 += nh;
+                        stat(ST_SIGNALS + 1, nh);
+                        continue;
+                    }
+                    const uint32_t n = t1 - h1;
+                    // a full first signal queue makes E fire what it has
+                    if (room && free2 && n && (n >= EW || fdone || pend == SQ)) {
+                        e = min(n, EW);
+                        // at most free2 signals can pass on: the first that cannot bounds the ensemble
+                        const uint32_t nle = (uint32_t)__popcll(
+                            __ballot(((t - sh1) & (SQ - 1u)) < pend && sq1 - h1 <= e));
+                        if (nle > free2) e = __builtin_amdgcn_readlane(sq1, (sh1 + free2) & (SQ - 1u)) - h1;
+                    }
+                }
+                if constexpr (!WALK) {
                     if (sh1 < st1) {
                         pending = true;
                         const uint32_t p = __builtin_amdgcn_readlane(sq1, sh1 & (SQ - 1u));
@@ -1122,14 +1250,45 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
             }
             // ---------------- F
-            if (!fdone) {
+            if constexpr (LANES) {
+                if (!fdone) {
+                    uint32_t e = min(EW, vend - fpos);
+                    // region ends at or before fpos + e not yet signalled: lane q looks at region
+                    // jb + q (ends grow with the region index, so the hits form a prefix)
+                    const uint32_t jq = jb + t;
+                    const bool in = jq < nb && VT[min(jq + 1u, nb)] - fpos <= e;
+                    const uint32_t nall = (uint32_t)__popcll(__ballot(in));
+                    const uint32_t nbound = min(nall, SQ - (st1 - sh1));
+                    // the first end left unsignalled bounds the ensemble (sender rule: S1 has room)
+                    if (jb + nbound < nb) {
+                        const uint32_t nxt = uni(VT[jb + nbound + 1u]) - fpos;
+                        e = min(e, nxt);
+                    }
+                    // room for every item (all might pass)
+                    if ((e || nbound) && D1 - (t1 - h1) >= e) {
+                        if (e == EW) {
+                            f_node(BoolC<true>{}, e, nbound);
+                        } else if (e) {
+                            f_node(BoolC<false>{}, e, nbound);
+                        } else {   // ends with no item before them: signals only
+                            const uint32_t i = (t - st1) & (SQ - 1u);
+                            sq1 = i < nbound ? t1 : sq1;
+                            st1 += nbound;
+                            jb += nbound;
+                            stat(ST_SIGNALS + 0, nbound);
+                        }
+                        fdone = (fpos == vend && jb == nb);
+                        continue;
+                    }
+                }
+            } else if (!fdone) {
                 const uint32_t lim = TAG ? vend : rend;
                 const uint32_t e = min(EW, lim - fpos);
                 const bool ends = !TAG && fpos + e == rend;
                 // room for every item (all might pass) and, at a region's end, for its signal
                 if (D1 - (t1 - h1) >= e && (!ends || st1 - sh1 < SQ)) {
-                    if (e == EW) f_node(BoolC<true>{}, e);
-                    else if (e) f_node(BoolC<false>{}, e);
+                    if (e == EW) f_node(BoolC<true>{}, e, 0u);
+                    else if (e) f_node(BoolC<false>{}, e, 0u);
                     if constexpr (TAG) {
                         fdone = (fpos == vend);
                     } else if (ends) {
@@ -1155,7 +1314,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             break;
         }
 
-        if constexpr (TAG) flush_wave(utag);
+        if constexpr (WALK) flush_wave(utag);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no staged copy outlives the claim
         order();
         if (failed && t == 0) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1198,9 +1357,29 @@ static KernelFn pick_width(uint32_t w) {
     }
 }
 
+// Lane-resolved signals: u32 kinds, w up to 256.
+template <int KIND>
+static KernelFn pick_lanes(uint32_t w) {
+    if constexpr (KIND == RS_TEXT_WORDS) {
+        return nullptr;
+    } else {
+        switch (w) {
+            case 64: return rs_pipeline<KIND, RS_SIGNAL_LANES, 1>;
+            case 128: return rs_pipeline<KIND, RS_SIGNAL_LANES, 2>;
+            case 256: return rs_pipeline<KIND, RS_SIGNAL_LANES, 4>;
+            default: return nullptr;
+        }
+    }
+}
+
 template <int KIND>
 static KernelFn pick_strategy(uint32_t s, uint32_t w) {
-    return s == RS_TAG ? pick_width<KIND, RS_TAG>(w) : s == RS_SIGNAL ? pick_width<KIND, RS_SIGNAL>(w) : nullptr;
+    switch (s) {
+        case RS_TAG: return pick_width<KIND, RS_TAG>(w);
+        case RS_SIGNAL: return pick_width<KIND, RS_SIGNAL>(w);
+        case RS_SIGNAL_LANES: return pick_lanes<KIND>(w);
+        default: return nullptr;
+    }
 }
 
 static KernelFn pick(uint32_t kind, uint32_t s, uint32_t w) {

@@ -245,7 +245,7 @@ bool cache_lookup(uint32_t kind, uint32_t emit, int bucket, uint32_t *strategy, 
     int b;
     bool found = false;
     while (fscanf(f, "%u %u %d %u %u", &k, &e, &b, &s, &w) == 5) {
-        if (k == kind && e == emit && b == bucket && s <= RS_SIGNAL && rs::kernel_supported(k, s, w)) {
+        if (k == kind && e == emit && b == bucket && s != RS_AUTO && rs::kernel_supported(k, s, w)) {
             *strategy = s;
             *width = w;
             found = true;   // the last line for a key wins
@@ -500,10 +500,12 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
     HIP_OR(hipEventCreate(&e0), RS_EDEVICE);
     HIP_OR(hipEventCreate(&e1), RS_EDEVICE);
     int rc = RS_OK;
-    for (uint32_t strat = RS_TAG; strat <= RS_SIGNAL && rc == RS_OK; ++strat) {
+    for (uint32_t strat : {(uint32_t)RS_TAG, (uint32_t)RS_SIGNAL, (uint32_t)RS_SIGNAL_LANES}) {
+        if (rc != RS_OK) break;
         if (want_s != RS_AUTO && strat != want_s) continue;
         for (uint32_t w : kWidths) {
             if (want_w && w != want_w) continue;
+            if (!rs::kernel_supported(p->d.kind, strat, w)) continue;
             p->strategy = strat;
             p->width = w;
             std::unique_ptr<Batch> b;
@@ -587,12 +589,16 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     if (d->abi_version != RS_ABI_VERSION)
         return fail(RS_EINVAL, "abi_version %u, library is %u", d->abi_version, RS_ABI_VERSION);
     if (d->kind < RS_MODFILTER || d->kind > RS_GRAPH_THRESH) return fail(RS_EINVAL, "unknown kind %u", d->kind);
-    if (d->strategy > RS_AUTO) return fail(RS_EINVAL, "unknown strategy %u", d->strategy);
+    if (d->strategy > RS_SIGNAL_LANES) return fail(RS_EINVAL, "unknown strategy %u", d->strategy);
+    if (d->strategy == RS_SIGNAL_LANES && !rs::kernel_supported(d->kind, RS_SIGNAL_LANES, d->ensemble_width ? d->ensemble_width : 64))
+        return fail(RS_EINVAL, "lane-resolved signals are offered for u32 kinds only");
     if (d->agg_fields == 0 || (d->agg_fields & ~15u))
         return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX");
     const uint32_t w = d->ensemble_width;
     if (w && !rs::kernel_supported(d->kind, RS_TAG, w))
         return fail(RS_EINVAL, "ensemble_width %u not supported (64, 128, 256, 512 or 1024)", w);
+    if (w && d->strategy == RS_SIGNAL_LANES && !rs::kernel_supported(d->kind, RS_SIGNAL_LANES, w))
+        return fail(RS_EINVAL, "lane-resolved signals take ensemble_width 64, 128 or 256");
     if (d->queue_depth) {
         const uint32_t q = d->queue_depth;
         if (q & (q - 1)) return fail(RS_EINVAL, "queue_depth must be a power of two");

@@ -15,7 +15,19 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 STRATS = [rs.RS_TAG, rs.RS_SIGNAL]
-SNAME = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal"}
+# with lane-resolved signals, offered for u32 kinds at widths up to 256
+ALL3 = STRATS + [rs.RS_SIGNAL_LANES]
+SNAME = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal", rs.RS_SIGNAL_LANES: "lanes"}
+
+
+def strats(kind, width):
+    """The strategies offered for a kind and an ensemble width."""
+    return ALL3 if kind != rs.RS_TEXT_WORDS and width <= 256 else STRATS
+
+
+def skip_unoffered(kind, strategy, width):
+    if strategy not in strats(kind, width):
+        pytest.skip("lane-resolved signals are offered for u32 kinds at widths up to 256")
 ALL = rs.RS_COUNT | rs.RS_SUM | rs.RS_MIN | rs.RS_MAX
 
 
@@ -64,12 +76,13 @@ def run_one(kind, strategy, width, offsets, elements, lengths=None, parent_param
 
 @pytest.mark.parametrize("name", ["e1_modfilter.json", "e2_hash_expand.json", "e3_text_words.json",
                                   "e4_graph_thresh.json"])
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 @pytest.mark.parametrize("width", [64, 256])
 def test_golden_streams(name, strategy, width):
     g = json.load(open(os.path.join(GOLDEN, name)))
     say("golden", name, SNAME[strategy], width)
     kind = g["kind"]
+    skip_unoffered(kind, strategy, width)
     if kind == rs.RS_TEXT_WORDS:
         elems = np.frombuffer(g["text"].encode(), np.uint8)
         got, _ = run_one(kind, strategy, width, np.array(g["starts"], np.uint32), elems,
@@ -84,10 +97,11 @@ def test_golden_streams(name, strategy, width):
 
 # ---- sum app, 4096 parents with sizes in [0, 64] ----
 
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 @pytest.mark.parametrize("width", [64, 128, 256, 512])
 @pytest.mark.parametrize("device", [False, True])
 def test_sum_app_4096_parents(strategy, width, device):
+    skip_unoffered(rs.RS_MODFILTER, strategy, width)
     say("sum app", SNAME[strategy], width, "device" if device else "host")
     offsets, vals = workloads.modfilter_workload(seed=1, n_parents=4096, max_size=64)
     ref = oracle.run(oracle.MODFILTER, offsets, vals, param=(4, 0, 0, 0))
@@ -100,7 +114,7 @@ def test_sum_app_4096_parents(strategy, width, device):
 def test_modfilter_parameters(modulus, residue):
     offsets, vals = workloads.modfilter_workload(seed=17, n_parents=3000, max_size=90)
     ref = oracle.run(oracle.MODFILTER, offsets, vals, param=(modulus, residue, 0, 0))
-    for strategy in STRATS:
+    for strategy in ALL3:
         got, _ = run_one(rs.RS_MODFILTER, strategy, 256, offsets, vals, param=(modulus, residue, 0, 0))
         check(got, ref, where=f"mod {modulus} {residue}")
 
@@ -108,7 +122,7 @@ def test_modfilter_parameters(modulus, residue):
 # ---- boundary-frequency sweep, reduced size: several tiles and a ragged tail ----
 
 @pytest.mark.parametrize("L", [1, 4, 16, 64, 256, 1024, 4096])
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 def test_hash_expand_fixed_L(L, strategy):
     n = (1 << 18) + 13                     # not a multiple of the region length or of 4
     say("hash/expand L", L, SNAME[strategy])
@@ -120,8 +134,9 @@ def test_hash_expand_fixed_L(L, strategy):
 
 
 @pytest.mark.parametrize("width", [64, 128, 512])
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 def test_hash_expand_widths_variable_regions(width, strategy):
+    skip_unoffered(rs.RS_HASH_EXPAND, strategy, width)
     say("hash/expand width", width, SNAME[strategy])
     offsets = workloads.uniform_offsets(5, 3000, 300)
     vals = workloads.hash_values(5, int(offsets[-1]))
@@ -132,7 +147,7 @@ def test_hash_expand_widths_variable_regions(width, strategy):
 
 # ---- edge cases ----
 
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 def test_edge_cases(strategy):
     say("edge cases", SNAME[strategy])
     # all parents empty
@@ -187,7 +202,7 @@ def test_text_long_lines_and_long_words(strategy):
     check(got, ref, where="text long")
 
 
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 @pytest.mark.parametrize("width", [64, 256])
 def test_graph_threshold(strategy, width):
     say("graph", SNAME[strategy], width)
@@ -203,7 +218,7 @@ def test_batched_streams_equal_alone():
     say("batched")
     shapes = [(5000, 1.0), (20000, 37.5), (100000, 700.0), (3000, 4096.0), (1, 1.0), (77777, 3.0)]
     streams = [workloads.serving_stream(5, s, n, m) for s, (n, m) in enumerate(shapes)]
-    for strategy in STRATS:
+    for strategy in ALL3:
         with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:
             ids = [p.push(o, v) for o, v in streams]
             p.run()
@@ -215,7 +230,7 @@ def test_run_again_replays_bit_exact():
     offsets = workloads.fixed_offsets(1 << 20, 64)
     vals = workloads.hash_values(2, 1 << 20)
     ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
-    for strategy in STRATS:
+    for strategy in ALL3:
         with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:
             sid = p.push(offsets, vals)
             p.run()
@@ -240,7 +255,7 @@ def test_signal_occupancy_matches_closed_form():
         assert st_t.items[0] == n and st_t.signals[0] == 0
 
 
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 @pytest.mark.parametrize("mx", [1, 7, 64, 300, 5000])
 def test_variable_size_regions(strategy, mx):
     """Region sizes uniform in [0, max] (the variable-size sweep): records equal the oracle's,
@@ -261,6 +276,45 @@ def test_variable_size_regions(strategy, mx):
             assert st.signals[0] == len(sizes)
 
 
+def test_lane_signals_flow_and_occupancy():
+    """Lane-resolved signals: every region's end is signalled once on each edge (empty regions
+    included), and ensembles span boundaries, so the enumerating node stays near full where the
+    plain signal strategy fills L/(w ceil(L/w)) of its lanes."""
+    w = 256
+    for L in (1, 5, 100, 300):
+        n = 200003
+        offsets = workloads.fixed_offsets(n, L)
+        vals = workloads.hash_values(2, n)
+        P = len(offsets) - 1
+        got, st = run_one(rs.RS_HASH_EXPAND, rs.RS_SIGNAL_LANES, w, offsets, vals, flags=rs.RS_COLLECT_STATS)
+        check(got, oracle.run(oracle.HASH_EXPAND, offsets, vals), where=f"lanes L={L}")
+        assert st.items[0] == n
+        assert st.signals[0] == P and st.signals[1] == P and st.signals[2] == P
+        occ = st.items[0] / (st.firings[0] * w)
+        if L >= 64:
+            # a firing is cut short only at the end of a claim
+            assert occ > 0.9, (L, occ)
+        else:
+            # the 64-entry signal queue bounds an ensemble to the regions whose ends fit in it,
+            # still far above the plain signal strategy's L / (w ceil(L/w))
+            assert occ > 2 * L / (w * -(-L // w)), (L, occ)
+    # empty regions everywhere between single elements
+    offsets = np.repeat(np.arange(0, 1001, dtype=np.uint32), 3)
+    vals = workloads.hash_values(3, 1000)
+    got, st = run_one(rs.RS_HASH_EXPAND, rs.RS_SIGNAL_LANES, 64, offsets, vals, flags=rs.RS_COLLECT_STATS)
+    check(got, oracle.run(oracle.HASH_EXPAND, offsets, vals), where="lanes empty regions")
+    assert st.signals[0] == len(offsets) - 1
+
+
+def test_lane_signals_not_offered_for_text_or_wide_ensembles():
+    with pytest.raises(rs.RsError) as ei:
+        rs.Pipeline(rs.RS_TEXT_WORDS, strategy=rs.RS_SIGNAL_LANES, ensemble_width=64)
+    assert ei.value.code == rs.RS_EINVAL
+    with pytest.raises(rs.RsError) as ei:
+        rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_SIGNAL_LANES, ensemble_width=512)
+    assert ei.value.code == rs.RS_EINVAL
+
+
 # ---- ordered output stream ----
 
 def run_outputs(kind, strategy, width, offsets, elements, lengths=None, parent_param=None):
@@ -270,7 +324,7 @@ def run_outputs(kind, strategy, width, offsets, elements, lengths=None, parent_p
         return p.read(sid), p.outputs(sid)
 
 
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 @pytest.mark.parametrize("L", [1, 7, 300, 5000])
 def test_output_stream_hash_expand(strategy, L):
     say("outputs hash/expand", SNAME[strategy], L)
@@ -283,20 +337,22 @@ def test_output_stream_hash_expand(strategy, L):
     assert len(out) == len(ref.out) and np.array_equal(out, ref.out)
 
 
-@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("strategy", ALL3)
 def test_output_stream_other_kinds(strategy):
     say("outputs other kinds", SNAME[strategy])
     offsets, vals = workloads.modfilter_workload(seed=1, n_parents=4096, max_size=64)
     ref = oracle.run(oracle.MODFILTER, offsets, vals, emit_outputs=True)
     _, out = run_outputs(rs.RS_MODFILTER, strategy, 128, offsets, vals)
     assert np.array_equal(out, ref.out)
-    text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 19)
-    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths, emit_outputs=True)
-    _, out = run_outputs(rs.RS_TEXT_WORDS, strategy, 256, starts, text, lengths=lengths)
-    assert np.array_equal(out, ref.out)
     offsets, w, thr, _ = workloads.graph_workload(seed=4, n_vertices=1 << 13, n_edges=1 << 17, cap=20000)
     ref = oracle.run(oracle.GRAPH_THRESH, offsets, w, parent_param=thr, emit_outputs=True)
     _, out = run_outputs(rs.RS_GRAPH_THRESH, strategy, 64, offsets, w, parent_param=thr)
+    assert np.array_equal(out, ref.out)
+    if strategy not in strats(rs.RS_TEXT_WORDS, 256):
+        return
+    text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 19)
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths, emit_outputs=True)
+    _, out = run_outputs(rs.RS_TEXT_WORDS, strategy, 256, starts, text, lengths=lengths)
     assert np.array_equal(out, ref.out)
 
 
@@ -304,7 +360,7 @@ def test_output_stream_batched_and_replayed():
     say("outputs batched/replayed")
     shapes = [(5000, 1.0), (60000, 37.5), (100000, 700.0), (1, 1.0)]
     streams = [workloads.serving_stream(5, s, n, m) for s, (n, m) in enumerate(shapes)]
-    for strategy in STRATS:
+    for strategy in ALL3:
         with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256, emit_outputs=True) as p:
             ids = [p.push(o, v) for o, v in streams]
             p.run()
@@ -326,7 +382,7 @@ def test_malformed_device_regions_are_rejected():
     bad_offsets = [np.array([0, 100, 50, 4096], np.uint32),          # decreasing
                    np.array([0, 100, 5000], np.uint32)]               # past n_elements
     for offs in bad_offsets:
-        for strategy in STRATS:
+        for strategy in ALL3:
             with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:
                 sid = p.push(torch.from_numpy(offs.view(np.int32)).cuda(), vals, n_elements=4096)
                 p.run()
