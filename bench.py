@@ -134,7 +134,7 @@ def variable_sweep(rs, torch, stream, copies, steps, warmup, width=0):
         R = len(sizes)
         offsets = torch.from_numpy(offs_h.view(np.int32)).cuda()
         row = {"max": mx, "regions": R}
-        for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+        for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal"), (rs.RS_SIGNAL_LANES, "lanes")):
             ms, kt, w, _ = time_config(rs, torch, stream, offsets, copies, s, width, steps, warmup)
             kms = kt["mean"]
             nbytes = 4 * N_ELEMENTS + 4 * (R + 1) + 20 * R
@@ -155,7 +155,7 @@ def output_stream_rate(rs, torch, stream, vals, L, steps=5):
     pipeline kernel's median, and algorithmic bytes with 4 B per output item added."""
     offsets = torch.from_numpy(__import__("workloads").fixed_offsets(N_ELEMENTS, L).view(np.int32)).cuda()
     res = {}
-    for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+    for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal"), (rs.RS_SIGNAL_LANES, "lanes")):
         with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=s, ensemble_width=0, emit_outputs=True,
                          flags=rs.RS_TIME_KERNEL) as p:
             p.set_stream(stream.cuda_stream)
@@ -307,7 +307,10 @@ def other_configs(rs, torch, stream, steps=5):
 
     def kernel_rate(kind, offsets, elements, n_bytes_alg, lengths=None, parent_param=None, fields=None, param=None):
         res = {}
-        for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+        strats = ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal"))
+        if kind != rs.RS_TEXT_WORDS:
+            strats += ((rs.RS_SIGNAL_LANES, "lanes"),)
+        for s, name in strats:
             kw = {} if param is None else {"param": param}
             with rs.Pipeline(kind, strategy=s, ensemble_width=0, agg_fields=fields, flags=rs.RS_TIME_KERNEL,
                              **kw) as p:
@@ -334,7 +337,7 @@ def other_configs(rs, torch, stream, steps=5):
     offsets, vals = workloads.modfilter_workload(seed=1)
     o, v = dev(offsets), dev(vals)
     c1 = {}
-    for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal")):
+    for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal"), (rs.RS_SIGNAL_LANES, "lanes")):
         with rs.Pipeline(rs.RS_MODFILTER, strategy=s, ensemble_width=0, agg_fields=rs.RS_COUNT | rs.RS_SUM,
                          param=(4, 0, 0, 0)) as p:
             p.set_stream(stream.cuda_stream)
@@ -452,7 +455,8 @@ def main():
     ap.add_argument("--width", type=int, default=0, help="ensemble width; 0 lets the autotuner choose")
     ap.add_argument("--headline-only", action="store_true", help="time only L = 4096 (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--strategy", choices=["tag", "signal", "both"], default="both")
+    ap.add_argument("--strategy", choices=["tag", "signal", "lanes", "both", "all"], default="all",
+                    help="lanes: the lane-resolved signals the paper proposes as future work")
     ap.add_argument("--no-occupancy", action="store_true", help="skip the per-node statistics pass of the sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the 512-stream batching/serving leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1/C3/C4 workloads")
@@ -476,8 +480,10 @@ def main():
               for c in range(COPIES)]
     print(f"[bench] generated {COPIES} x 2^26 elements in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
           flush=True)
-    strategies = {"tag": [rs.RS_TAG], "signal": [rs.RS_SIGNAL], "both": [rs.RS_TAG, rs.RS_SIGNAL]}[args.strategy]
-    names = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal"}
+    strategies = {"tag": [rs.RS_TAG], "signal": [rs.RS_SIGNAL], "lanes": [rs.RS_SIGNAL_LANES],
+                  "both": [rs.RS_TAG, rs.RS_SIGNAL],
+                  "all": [rs.RS_TAG, rs.RS_SIGNAL, rs.RS_SIGNAL_LANES]}[args.strategy]
+    names = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal", rs.RS_SIGNAL_LANES: "lanes"}
     lengths = [HEADLINE_L] if args.headline_only else LENGTHS
     sweep = []
     head = {}

@@ -789,8 +789,13 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if constexpr (BYTES) ls = uni(SX[0]);
             }
         }
-        // lane-resolved signals: the next region whose end the enumerating node has not signalled
+        // lane-resolved signals: the next region whose end the enumerating node has not signalled,
+        // and that end
         uint32_t jb = 0;
+        uint32_t bnext = 0;
+        if constexpr (LANES) {
+            if (nb) bnext = uni(VT[1]);
+        }
         // lane-resolved signals finish once every position is enumerated and every region's end
         // is signalled (empty regions included)
         bool fdone = LANES ? (vbeg >= vend && nb == 0) : TAG ? (vbeg >= vend) : (nb == 0);
@@ -1035,15 +1040,17 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint32_t rel = sq1 - h1;
                 const bool fw = ((t - sh1) & (SQ - 1u)) < pend && rel <= taken;
                 const uint32_t nf = min((uint32_t)__popcll(__ballot(fw)), free2);
-                const uint32_t r = fw ? rel : 0u;
-                const uint32_t np = t2 + bits_below<V>(b0, r) + 2u * bits_below<V>(b1, r);
-                // S1 entry sh1 + i becomes S2 entry st2 + i
-                const uint32_t i = (t - st2) & (SQ - 1u);
-                const uint32_t moved = (uint32_t)__shfl((int)np, (int)((sh1 + i) & (SQ - 1u)), 64);
-                sq2 = i < nf ? moved : sq2;
-                st2 += nf;
-                sh1 += nf;
-                stat(ST_SIGNALS + 1, nf);
+                if (nf) {
+                    const uint32_t r = fw ? rel : 0u;
+                    const uint32_t np = t2 + bits_below<V>(b0, r) + 2u * bits_below<V>(b1, r);
+                    // S1 entry sh1 + i becomes S2 entry st2 + i
+                    const uint32_t i = (t - st2) & (SQ - 1u);
+                    const uint32_t moved = (uint32_t)__shfl((int)np, (int)((sh1 + i) & (SQ - 1u)), 64);
+                    sq2 = i < nf ? moved : sq2;
+                    st2 += nf;
+                    sh1 += nf;
+                    stat(ST_SIGNALS + 1, nf);
+                }
             }
             h1 += taken;
             t2 += made;
@@ -1107,16 +1114,18 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
             }
             if constexpr (LANES) {
-                // each region end's signal sits at the queue position of the first kept item after
-                // it; lane i mod 64 holds signal-queue entry i
-                const uint32_t i = (t - st1) & (SQ - 1u);
-                const bool mine = i < nbound;
-                const uint32_t rel = mine ? min(VT[min(jb + i + 1u, nb)] - fpos, e) : 0u;
-                const uint32_t p = t1 + bits_below<V>(kb, rel);
-                sq1 = mine ? p : sq1;
-                st1 += nbound;
-                jb += nbound;
-                stat(ST_SIGNALS + 0, nbound);
+                if (nbound) {
+                    // each region end's signal sits at the queue position of the first kept item
+                    // after it; lane i mod 64 holds signal-queue entry i
+                    const uint32_t i = (t - st1) & (SQ - 1u);
+                    const bool mine = i < nbound;
+                    const uint32_t rel = mine ? min(VT[min(jb + i + 1u, nb)] - fpos, e) : 0u;
+                    const uint32_t p = t1 + bits_below<V>(kb, rel);
+                    sq1 = mine ? p : sq1;
+                    st1 += nbound;
+                    jb += nbound;
+                    stat(ST_SIGNALS + 0, nbound);
+                }
             }
             if constexpr (!BYTES) stage(fpos + e);   // the slot's contents are in registers
             t1 += run;
@@ -1253,16 +1262,21 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             if constexpr (LANES) {
                 if (!fdone) {
                     uint32_t e = min(EW, vend - fpos);
-                    // region ends at or before fpos + e not yet signalled: lane q looks at region
-                    // jb + q (ends grow with the region index, so the hits form a prefix)
-                    const uint32_t jq = jb + t;
-                    const bool in = jq < nb && VT[min(jq + 1u, nb)] - fpos <= e;
-                    const uint32_t nall = (uint32_t)__popcll(__ballot(in));
-                    const uint32_t nbound = min(nall, SQ - (st1 - sh1));
-                    // the first end left unsignalled bounds the ensemble (sender rule: S1 has room)
-                    if (jb + nbound < nb) {
-                        const uint32_t nxt = uni(VT[jb + nbound + 1u]) - fpos;
-                        e = min(e, nxt);
+                    uint32_t nbound = 0;
+                    // the next end not yet signalled (kept in a register): most firings of long
+                    // regions hold none
+                    if (jb < nb && bnext - fpos <= e) {
+                        // region ends at or before fpos + e: lane q looks at region jb + q (ends
+                        // grow with the region index, so the hits form a prefix)
+                        const uint32_t jq = jb + t;
+                        const bool in = jq < nb && VT[min(jq + 1u, nb)] - fpos <= e;
+                        const uint32_t nall = (uint32_t)__popcll(__ballot(in));
+                        nbound = min(nall, SQ - (st1 - sh1));
+                        // the first end left unsignalled bounds the ensemble (sender rule: S1 has room)
+                        if (jb + nbound < nb) {
+                            const uint32_t nxt = uni(VT[jb + nbound + 1u]) - fpos;
+                            e = min(e, nxt);
+                        }
                     }
                     // room for every item (all might pass)
                     if ((e || nbound) && D1 - (t1 - h1) >= e) {
@@ -1278,6 +1292,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                             stat(ST_SIGNALS + 0, nbound);
                         }
                         fdone = (fpos == vend && jb == nb);
+                        if (nbound && jb < nb) bnext = uni(VT[jb + 1u]);
                         continue;
                     }
                 }

@@ -14,7 +14,8 @@ import paper_2006_07478_amd as rs
 pytestmark = pytest.mark.gpu
 
 STRATS = [rs.RS_TAG, rs.RS_SIGNAL]
-SNAME = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal"}
+ALL3 = STRATS + [rs.RS_SIGNAL_LANES]   # lane-resolved signals: u32 kinds
+SNAME = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal", rs.RS_SIGNAL_LANES: "lanes"}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -59,7 +60,7 @@ def test_hash_expand_2p26(L):
     offsets = workloads.fixed_offsets(n, L)
     vals = workloads.hash_values(2, n)
     ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
-    for s in STRATS:
+    for s in ALL3:
         say("2^26 hash/expand L", L, SNAME[s])
         got, st = run_dev(rs.RS_HASH_EXPAND, s, offsets, vals)
         say("   ensemble width", st.ensemble_width)
@@ -73,7 +74,7 @@ def test_variable_sizes_2p26(mx):
     offsets = workloads.variable_offsets(13, n, mx)
     vals = workloads.hash_values(2, n)
     ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
-    for s in STRATS:
+    for s in ALL3:
         say("2^26 variable sizes max", mx, SNAME[s])
         got, st = run_dev(rs.RS_HASH_EXPAND, s, offsets, vals)
         check(got, ref, ("count", "sum", "min", "max"), f"2^26 variable max={mx} {SNAME[s]}")
@@ -94,7 +95,7 @@ def test_graph_2p24_vertices_2p28_edges():
     offsets, w, thr, beta = workloads.graph_workload(seed=4)
     say("graph: beta", beta, "max degree", int(np.diff(offsets.astype(np.int64)).max()))
     ref = oracle.run(oracle.GRAPH_THRESH, offsets, w, parent_param=thr)
-    for s in STRATS:
+    for s in ALL3:
         say("graph", SNAME[s])
         got, st = run_dev(rs.RS_GRAPH_THRESH, s, offsets, w, parent_param=thr, fields=rs.RS_COUNT | rs.RS_SUM)
         check(got, ref, ("count", "sum"), f"graph {SNAME[s]}")
