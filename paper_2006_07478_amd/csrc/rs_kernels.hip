@@ -654,16 +654,32 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             return l2;
         };
-        // Regions of the items fpos_ + k*64 + lane (tag strategy; the first e are real).  jlo_ is
-        // the region of the first item; one_ says every item lies in it.
+        // Regions of the items fpos_ + k*64 + lane (the first e are real; the others get a region
+        // in range).  jlo_ is the region of the first item; one_ says every item lies in it.
         auto f_regions = [&](auto full, uint32_t fpos_, uint32_t e, uint32_t jlo_, bool one_, uint32_t (&reg)[V]) {
             constexpr bool FULL = decltype(full)::value;
+            const uint32_t *key = BYTES ? SX : VT;
+            const uint32_t last = fpos_ + e - 1u;   // position of the ensemble's last item
+            if (one_) {
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const uint32_t i = (uint32_t)k * 64u + t;
-                if (one_) {
-                    reg[k] = jlo_;
-                } else {
+                for (int k = 0; k < V; ++k) reg[k] = jlo_;
+            } else if (jlo_ + 8u >= nb || uni(key[jlo_ + 8u]) > last) {
+                // at most eight region starts inside the ensemble: one uniform pass over them,
+                // each lane counting the starts at or before its item (equal starts, i.e. empty
+                // regions, all count)
+#pragma unroll
+                for (int k = 0; k < V; ++k) reg[k] = jlo_;
+                for (uint32_t j = jlo_ + 1u; j < nb; ++j) {
+                    const uint32_t st = uni(key[j]);
+                    if (st > last) break;
+#pragma unroll
+                    for (int k = 0; k < V; ++k) reg[k] += fpos_ + (uint32_t)k * 64u + t >= st ? 1u : 0u;
+                }
+            } else {
+                // many short regions: a binary search per lane
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const uint32_t i = (uint32_t)k * 64u + t;
                     jlo_ = f_region(fpos_ + (FULL || i < e ? i : 0u), jlo_);   // positions grow with k
                     reg[k] = jlo_;
                 }
