@@ -915,9 +915,25 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
 #pragma unroll
                 for (int k = 0; k < V; ++k) acc_add(acc, y[k], FULL || (uint32_t)k * 64u + t < e);
+            } else if (tl - tf < 8u) {
+                // the ensemble spans a few regions: one wave reduction per region that ends in it,
+                // whose total one lane adds to the region's slot (per-lane flushes would pile onto
+                // the same slot); the last region stays open in the accumulators
+                if (tf != utag) {
+                    flush_wave(utag);
+                    utag = tf;
+                }
+                for (uint32_t r = tf; r < tl; ++r) {
+#pragma unroll
+                    for (int k = 0; k < V; ++k) acc_add(acc, y[k], (FULL || (uint32_t)k * 64u + t < e) && tg[k] == r);
+                    flush_wave(r);
+                }
+#pragma unroll
+                for (int k = 0; k < V; ++k) acc_add(acc, y[k], (FULL || (uint32_t)k * 64u + t < e) && tg[k] == tl);
+                utag = tl;
             } else {
-                // the ensemble crosses region boundaries: each lane flushes where its own items
-                // change region (tags grow along the queue), then every lane flushes at the end
+                // the ensemble crosses many region boundaries: each lane flushes where its own
+                // items change region (tags grow along the queue), then every lane flushes at the end
                 uint32_t lt = utag;
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
