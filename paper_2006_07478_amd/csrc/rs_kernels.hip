@@ -915,10 +915,11 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
 #pragma unroll
                 for (int k = 0; k < V; ++k) acc_add(acc, y[k], FULL || (uint32_t)k * 64u + t < e);
-            } else if (tl - tf < 8u) {
-                // the ensemble spans a few regions: one wave reduction per region that ends in it,
-                // whose total one lane adds to the region's slot (per-lane flushes would pile onto
-                // the same slot); the last region stays open in the accumulators
+            } else if (tl - tf < 8u && (tl - tf + 1u) * 16u <= e) {
+                // the ensemble spans a few regions of many items each: one wave reduction per
+                // region that ends in it, whose total one lane adds to the region's slot (per-lane
+                // flushes would pile onto the same slot); the last region stays open in the
+                // accumulators
                 if (tf != utag) {
                     flush_wave(utag);
                     utag = tf;
