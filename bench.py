@@ -35,12 +35,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hash_expand_L4096.json")
 
 
 def kernel_source_hash():
-    """Hash of the pipeline kernel's device source: the file up to its host-side launch table,
-    so that a change to host code alone keeps counter summaries valid."""
+    """Hash of the pipeline kernel's device code: the file up to its host-side launch table,
+    with line comments and whitespace dropped, so that a change to host code or to comments
+    alone keeps counter summaries valid."""
     with open(KERNEL_SOURCE, "rb") as f:
-        src = f.read()
-    cut = src.find(b"// ---------------------------------------------------------------- launch table")
-    return hashlib.sha256(src if cut < 0 else src[:cut]).hexdigest()[:16]
+        src = f.read().decode()
+    cut = src.find("// ---------------------------------------------------------------- launch table")
+    if cut >= 0:
+        src = src[:cut]
+    code = " ".join(line.split("//", 1)[0].strip() for line in src.splitlines())
+    return hashlib.sha256(" ".join(code.split()).encode()).hexdigest()[:16]
 
 
 def measured_traffic(strategy, width):

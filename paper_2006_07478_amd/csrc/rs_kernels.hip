@@ -3,8 +3,9 @@
 // One wave64 workgroup is one SIMD processor in the sense of §2.2: it runs a whole
 // pipeline instance (enumerating node F, optional second node E, aggregating node A)
 // under a non-preemptive scheduler whose state is wave-uniform and lives in scalar
-// registers, and it competes with every other wave for parent batches ("claims")
-// through a device atomic, returning only when every claim of the launch is done.
+// registers.  It takes parent batches ("claims") from its partition of the launch's
+// claims (eight partitions per XCD): most by index, the rest from the partition's
+// counter, then from other partitions, returning only when every claim is done.
 // A firing consumes an ensemble of at most w = 64*V items: item i sits on lane
 // i mod 64 in round i / 64, so one firing is V rounds of 64-lane SIMD work.
 //
@@ -19,7 +20,10 @@
 //     precedes it, running end() for that region.  S is one VGPR, entry n in lane
 //     n mod 64, read with readlane and written with a lane select (no LDS round trip); or
 //   - as tags (RS_TAG): every queued item carries its region index, ensembles mix
-//     regions freely, and the aggregating node reduces by tag (§5).
+//     regions freely, and the aggregating node reduces by tag (§5); or
+//   - as lane-resolved signals (RS_SIGNAL_LANES, the future work of §6): the signals and
+//     their queues of RS_SIGNAL, but ensembles may span them, and every node computes each
+//     lane's region from the pending signals' positions instead of storing it.
 // Aggregates are exact integer reductions kept in LDS slots per claim and written once
 // per parent; a claim always holds whole regions, so no aggregate is ever shared
 // between waves.
