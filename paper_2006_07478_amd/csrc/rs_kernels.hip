@@ -26,7 +26,11 @@
 //     lane's region from the pending signals' positions instead of storing it.
 // Aggregates are exact integer reductions kept in LDS slots per claim and written once
 // per parent; a claim always holds whole regions, so no aggregate is ever shared
-// between waves.
+// between waves.  How an ensemble reaches the slots depends on the regions it spans: one
+// region goes into per-lane accumulators; a few regions of many items each, one wave reduction
+// apiece; more regions, per-lane flushes where a lane's items change region, except that under
+// tags, when they average 8 or more items, the lanes of a region fold within each 8-lane block
+// first, so one lane per block adds to the slot.
 //
 // Elements reach the enumerating node from HBM through direct buffer->LDS loads into a
 // one-ensemble staging slot; the next firing's ensemble is requested as soon as the
@@ -269,6 +273,27 @@ __device__ __forceinline__ Acc wave_reduce(Acc a) {
     r.mn = (uint32_t)__builtin_amdgcn_readlane(a.mn, 63);
     r.mx = (uint32_t)__builtin_amdgcn_readlane(a.mx, 63);
     return r;
+}
+
+// Segmented inclusive scans inside 8-lane blocks, one field at a time: t1/t2/t4 say whether
+// lane t takes in lane t - 1/2/4's partial (that lane is in its block and carries the same key;
+// keys grow along the lanes, so an equal key some lanes back means the same segment).  Identity
+// values fill the lanes a shift reaches outside its row.
+template <int OP>   // 0: add, 1: min, 2: max
+__device__ __forceinline__ uint32_t seg_scan32(uint32_t v, bool t1, bool t2, bool t4) {
+    constexpr uint32_t ID = OP == 1 ? 0xFFFFFFFFu : 0u;
+    auto comb = [](uint32_t a, uint32_t b) { return OP == 0 ? a + b : OP == 1 ? min(a, b) : max(a, b); };
+    uint32_t p = dpp_or<0x111, 0xF>(ID, v);   // row_shr:1
+    v = t1 ? comb(v, p) : v;
+    p = dpp_or<0x112, 0xF>(ID, v);            // row_shr:2
+    v = t2 ? comb(v, p) : v;
+    p = dpp_or<0x114, 0xF>(ID, v);            // row_shr:4
+    return t4 ? comb(v, p) : v;
+}
+// The 64-bit sum as two 16-bit halves, each summed in 32 bits (a block has at most 8 lanes)
+__device__ __forceinline__ unsigned long long seg_sum64(uint32_t v, bool t1, bool t2, bool t4) {
+    const uint32_t lo = seg_scan32<0>(v & 0xFFFFu, t1, t2, t4), hi = seg_scan32<0>(v >> 16, t1, t2, t4);
+    return ((unsigned long long)hi << 16) + lo;
 }
 
 // Set bits among ensemble indices [0, rel) of the per-round masks m (index k*64 + lane is bit
@@ -936,9 +961,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) acc_add(acc, y[k], (FULL || (uint32_t)k * 64u + t < e) && tg[k] == tl);
                 utag = tl;
-            } else {
-                // the ensemble crosses many region boundaries: each lane flushes where its own
-                // items change region (tags grow along the queue), then every lane flushes at the end
+            } else if (!TAG || (tl - tf + 1u) * 8u > e) {
+                // regions of a few items each: each lane flushes where its own items change region
+                // (tags grow along the queue), then every lane flushes at the end
                 uint32_t lt = utag;
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
@@ -950,6 +975,37 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     acc_add(acc, y[k], act);
                 }
                 flush_lane(lt);
+                utag = tl;
+            } else {
+                // tags, many regions of 8 or more items on average: round by round, the lanes of
+                // one region inside each 8-lane block fold into that region's last lane in the
+                // block (a segmented scan over DPP row shifts), which alone adds to the region's
+                // slot; lanes of one region would otherwise serialise on the slot's atomics
+                if (__ballot(acc.cnt != 0u)) flush_wave(utag);   // what the accumulators hold
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const bool act = FULL || (uint32_t)k * 64u + t < e;
+                    const uint32_t key = act ? tg[k] : 0xFFFFFFFFu;   // no region has this key
+                    // every lane reads its neighbours' keys before any lane-dependent test: a DPP
+                    // read under a partial exec mask sees disabled source lanes as out of range
+                    const uint32_t k1 = dpp_or<0x111, 0xF>(0xFFFFFFFEu, key);   // row_shr:1
+                    const uint32_t k2 = dpp_or<0x112, 0xF>(0xFFFFFFFEu, key);   // row_shr:2
+                    const uint32_t k4 = dpp_or<0x114, 0xF>(0xFFFFFFFEu, key);   // row_shr:4
+                    const uint32_t kn = dpp_or<0x101, 0xF>(0xFFFFFFFFu, key);   // row_shl:1
+                    const uint32_t b = t & 7u;
+                    const bool t1 = (b >= 1u) & (k1 == key), t2 = (b >= 2u) & (k2 == key),
+                               t4 = (b >= 4u) & (k4 == key);
+                    // the block's last lane of a region: the block ends, or the next lane's key differs
+                    const bool lead = act & ((b == 7u) | (kn != key));
+                    const uint32_t c = seg_scan32<0>(act ? 1u : 0u, t1, t2, t4);
+                    if (lead) atomicAdd(&s_cnt[key], c);
+                    const unsigned long long sm = seg_sum64(act ? y[k] : 0u, t1, t2, t4);
+                    if (lead) atomicAdd(&s_sum[key], sm);
+                    const uint32_t mn = seg_scan32<1>(act ? y[k] : 0xFFFFFFFFu, t1, t2, t4);
+                    if (lead) atomicMin(&s_min[key], mn);
+                    const uint32_t mx = seg_scan32<2>(act ? y[k] : 0u, t1, t2, t4);
+                    if (lead) atomicMax(&s_max[key], mx);
+                }
                 utag = tl;
             }
             if constexpr (LANES) {

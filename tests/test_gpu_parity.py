@@ -276,6 +276,28 @@ def test_variable_size_regions(strategy, mx):
             assert st.signals[0] == len(sizes)
 
 
+@pytest.mark.parametrize("width", [64, 128, 256, 512, 1024])
+def test_tags_many_mid_size_regions(width):
+    """Tags, ensembles that span many regions of several items each (the lanes of one region fold
+    within each 8-lane block before one of them adds to the region's slot), at every width.  Hash
+    values use all 32 bits, so the folded sums carry past 32 bits; all-ones values, which a mod-4
+    filter with residue 3 keeps, fill both 16-bit halves of every folded sum."""
+    say("tags, mid-size regions, width", width)
+    n = 200003
+    offsets = workloads.variable_offsets(21, n, 48)   # sizes U[0, 48]: about 18 items a region
+    vals = workloads.hash_values(22, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    got, _ = run_one(rs.RS_HASH_EXPAND, rs.RS_TAG, width, offsets, vals)
+    check(got, ref, where=f"hash/expand, sizes U[0,48], w={width}")
+    m = (1 << 17) + 5
+    offsets = workloads.fixed_offsets(m, 17)
+    ones = np.full(m, 0xFFFFFFFF, np.uint32)
+    ref = oracle.run(oracle.MODFILTER, offsets, ones, param=(4, 3, 0, 0))
+    assert int(ref.count[0]) == 17 and int(ref.sum[0]) == 17 * 0xFFFFFFFF
+    got, _ = run_one(rs.RS_MODFILTER, rs.RS_TAG, width, offsets, ones, param=(4, 3, 0, 0))
+    check(got, ref, where=f"all-ones, L=17, w={width}")
+
+
 def test_lane_signals_flow_and_occupancy():
     """Lane-resolved signals: every region's end is signalled once on each edge (empty regions
     included), and ensembles span boundaries, so the enumerating node stays near full where the
