@@ -308,10 +308,16 @@ hipStream_t lane_of(rs_pipeline *p, uint64_t batch_id) {
 // ---------------------------------------------------------------- batches
 
 // Claim size: about 16 ensembles of elements per claim, at most claim_parents_max(w)
-// parents, at least one parent.
-void plan_claims(Stream *s, uint32_t width, uint32_t n_parents) {
+// parents, at least one parent.  An ordered output stream over u32 elements takes about 32 when
+// the stream still makes at least 2048 such claims (8 per compute unit): its claims start in
+// index order and each waits on its predecessor's output offset, so fewer, larger claims
+// shorten that chain.  Text lines, whose lengths vary widely, and streams with fewer claims keep
+// 16.
+void plan_claims(Stream *s, uint32_t kind, bool ordered_out, uint32_t width, uint32_t n_parents) {
     const double bmax = rs::claim_parents_max(width);
-    const double b = s->mean_len > 0 ? 16.0 * width / s->mean_len : bmax;
+    const bool big = ordered_out && kind != RS_TEXT_WORDS && s->mean_len > 0 &&
+                     (double)n_parents * s->mean_len >= 2048.0 * 32.0 * width;
+    const double b = s->mean_len > 0 ? (big ? 32.0 : 16.0) * width / s->mean_len : bmax;
     s->B = (uint32_t)std::max(1.0, std::min(bmax, b));
     s->n_claims = (uint32_t)(((uint64_t)n_parents + s->B - 1) / s->B);
 }
@@ -332,7 +338,7 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
         // so the timing ranks configurations as the full stream would
         if (probe && s->n_elements > (1u << 25) && P > 1)
             P = (uint32_t)std::max<uint64_t>(1, (uint64_t)((double)P * (double)(1u << 25) / s->n_elements));
-        plan_claims(s, p->width, P);
+        plan_claims(s, p->d.kind, p->d.emit_outputs && !probe, p->width, P);
         rs::StreamDev &e = h[i];
         std::memset(&e, 0, sizeof e);
         e.elements = s->elements;

@@ -67,6 +67,23 @@ def test_hash_expand_2p26(L):
         check(got, ref, ("count", "sum", "min", "max"), f"2^26 L={L} {SNAME[s]}")
 
 
+def test_output_stream_2p26():
+    """The ordered output stream at the headline size, as the benchmark times it (widths from the
+    autotuner): every output item in order, and the records."""
+    n = 1 << 26
+    offsets = workloads.fixed_offsets(n, 4096)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals, emit_outputs=True)
+    for s in ALL3:
+        say("2^26 output stream L 4096", SNAME[s])
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=s, ensemble_width=0, emit_outputs=True) as p:
+            sid = p.push(dev(offsets), dev(vals), n_elements=n)
+            p.run()
+            got, out = p.read(sid), p.outputs(sid)
+        check(got, ref, ("count", "sum", "min", "max"), f"2^26 outputs {SNAME[s]}")
+        assert len(out) == len(ref.out) and np.array_equal(out, ref.out), f"2^26 output items {SNAME[s]}"
+
+
 @pytest.mark.parametrize("mx", [16, 2048])
 def test_variable_sizes_2p26(mx):
     """The variable-size sweep at its full size: region sizes uniform in [0, max]."""

@@ -360,6 +360,21 @@ def test_output_stream_hash_expand(strategy, L):
 
 
 @pytest.mark.parametrize("strategy", ALL3)
+@pytest.mark.parametrize("L", [3, 37, 4096])
+def test_output_stream_large_claims(strategy, L):
+    """An ordered output stream of at least 2048 claims of 32 ensembles (w = 64: 2^22 elements and
+    up), where claims double in size: outputs and records equal the oracle's."""
+    say("outputs, large claims", SNAME[strategy], L)
+    n = (1 << 22) + 19
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(23, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals, emit_outputs=True)
+    got, out = run_outputs(rs.RS_HASH_EXPAND, strategy, 64, offsets, vals)
+    check(got, ref, where=f"outputs agg, L={L}")
+    assert len(out) == len(ref.out) and np.array_equal(out, ref.out)
+
+
+@pytest.mark.parametrize("strategy", ALL3)
 def test_output_stream_other_kinds(strategy):
     say("outputs other kinds", SNAME[strategy])
     offsets, vals = workloads.modfilter_workload(seed=1, n_parents=4096, max_size=64)
