@@ -84,9 +84,10 @@ def test_output_stream_2p26():
         assert len(out) == len(ref.out) and np.array_equal(out, ref.out), f"2^26 output items {SNAME[s]}"
 
 
-@pytest.mark.parametrize("mx", [16, 2048])
+@pytest.mark.parametrize("mx", [16, 32, 2048])
 def test_variable_sizes_2p26(mx):
-    """The variable-size sweep at its full size: region sizes uniform in [0, max]."""
+    """The variable-size sweep at its full size: region sizes uniform in [0, max] (max = 32: tags
+    fold many mid-size regions per 8-lane block)."""
     n = 1 << 26
     offsets = workloads.variable_offsets(13, n, mx)
     vals = workloads.hash_values(2, n)
