@@ -363,7 +363,8 @@ def test_output_stream_hash_expand(strategy, L):
 @pytest.mark.parametrize("L", [3, 37, 4096])
 def test_output_stream_large_claims(strategy, L):
     """An ordered output stream of at least 2048 claims of 32 ensembles (w = 64: 2^22 elements and
-    up), where claims double in size: outputs and records equal the oracle's."""
+    up), where claims hold twice the parents (at L = 4096 a claim is one parent either way):
+    outputs and records equal the oracle's."""
     say("outputs, large claims", SNAME[strategy], L)
     n = (1 << 22) + 19
     offsets = workloads.fixed_offsets(n, L)
