@@ -59,7 +59,8 @@ struct LaunchArgs {
     uint32_t emit_outputs;
     uint32_t bmax;                 // most parents in any claim of the launch (sizes the per-claim LDS)
     uint32_t n_parts;              // claim partitions: CTL_NPART, or 1 when claims must start in order
-    uint32_t pad[2];
+    uint32_t lb_wait_us;           // longest wait of one look-back step on a predecessor claim (microseconds)
+    uint32_t pad;
 };
 
 // Kernel entry points (defined in rs_kernels.hip).

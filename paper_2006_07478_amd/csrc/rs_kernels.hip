@@ -499,7 +499,15 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     // widx + Wp, widx + 2 Wp, ... for the partition's Wp waves; no atomic at all), then claims
     // from its home counter, and when that partition is used up, from the other partitions'
     // counters, found with one read of all of them.
+    //
+    // An ordered output stream is different: a claim waits in its look-back on every claim before
+    // it, so a claim must never belong to a wave that has not started.  Its claims come from one
+    // ascending counter only (one partition, none by index), so the claims taken at any moment are
+    // a prefix of the claim order and each belongs to a running wave; the smallest unfinished
+    // claim is then the current claim of a running wave, and every claim before it has published
+    // its count, whatever number of the launch's waves are resident.
     const uint32_t n_claims = a.total_claims, np = a.n_parts, n_waves = gridDim.x;
+    const bool by_index = a.emit_outputs == 0u;
     const uint32_t np_log = np == 1u ? 0u : 6u;   // n_parts is 1 or CTL_NPART = 64
     const uint32_t home = blockIdx.x & (np - 1u), widx = blockIdx.x >> np_log;
     auto p_begin = [&](uint32_t q) -> uint32_t { return (uint32_t)(((uint64_t)n_claims * q) >> np_log); };
@@ -507,7 +515,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     // claims each wave of partition q takes by index (at least two: the two claims in hand)
     auto p_static = [&](uint32_t q) -> uint32_t {
         const uint32_t wq = p_waves(q), size = p_begin(q + 1u) - p_begin(q);
-        return wq ? max(2u, size / 8u * 7u / wq) : 0u;
+        return (wq && by_index) ? max(2u, size / 8u * 7u / wq) : 0u;
     };
     const uint32_t home_static = p_static(home), home_waves = p_waves(home);
     const uint32_t home_begin = p_begin(home), home_end = p_begin(home + 1u);
@@ -548,7 +556,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         }
     };
 
-    // claims are taken two ahead: g is worked on, g1 is next (its region table in registers)
+    // claims are taken two ahead: g is worked on, g1 is next (its region table in registers).
+    // Under an ordered output stream this keeps the look-back's progress: the wave holding a
+    // claim is running, and it works its claims in increasing order.
     uint32_t g = take_claim();
     uint32_t g1 = take_claim();
     ClaimRegs<R> cur;
@@ -748,6 +758,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         };
 
         bool failed = false;
+        bool out_ok = true;   // the claim's output base is known (ordered output stream)
         // ---- ordered output stream: count this claim's outputs, then learn its base from the
         // claims before it (decoupled look-back over the stream's claims) before producing.
         unsigned long long out_rank = 0;
@@ -789,30 +800,53 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
             }
             // look-back: words are (epoch tag << 40) | (flag << 38) | value, flag 1 = this claim's
-            // own count, flag 2 = inclusive prefix through this claim
+            // own count, flag 2 = inclusive prefix through this claim, flag 3 = no valid prefix
+            // (a predecessor's look-back gave up).  Each wait on a predecessor is bounded in real
+            // time (s_memrealtime counts at 100 MHz): past the bound the claim publishes flag 3,
+            // writes no outputs and raises the launch's error flag, so every wave still finishes
+            // and the host reports a device error instead of waiting for ever.
             unsigned long long prefix = 0;
+            uint32_t lb_ok = 1;
             if (t == 0) {
                 GLOBAL unsigned long long *lb = sd.lookback;
                 const unsigned long long tagw = (unsigned long long)epoch_tag << 40;
                 const unsigned long long mask38 = (1ull << 38) - 1ull;
+                const unsigned long long limit = 100ull * a.lb_wait_us;
                 __hip_atomic_store(&lb[cidx], tagw | (1ull << 38) | (n_out & mask38), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
                 for (uint32_t i = cidx; i-- > 0;) {
-                    unsigned long long w;
+                    unsigned long long w = 0;
+                    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
                     for (;;) {
                         w = __hip_atomic_load(&lb[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if ((w >> 40) == (unsigned long long)epoch_tag && ((w >> 38) & 3ull)) break;
+                        if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                            w = 3ull << 38;
+                            break;
+                        }
                         __builtin_amdgcn_s_sleep(2);
+                    }
+                    if (((w >> 38) & 3ull) == 3ull) {
+                        lb_ok = 0;
+                        break;
                     }
                     prefix += w & mask38;
                     if (((w >> 38) & 3ull) == 2ull) break;
                 }
-                __hip_atomic_store(&lb[cidx], tagw | (2ull << 38) | ((prefix + n_out) & mask38), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                // the outputs must fit the stream's output array (k_max items per element)
+                const unsigned long long cap = (unsigned long long)sd.n_elements * KE;
+                if (prefix + n_out > cap) lb_ok = 0;
+                __hip_atomic_store(&lb[cidx],
+                                   lb_ok ? tagw | (2ull << 38) | ((prefix + n_out) & mask38) : tagw | (3ull << 38),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!lb_ok) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             out_rank = ((unsigned long long)uni((uint32_t)(prefix >> 32)) << 32) | uni((uint32_t)prefix);
+            lb_ok = uni(lb_ok);
+            if (!lb_ok) out_rank = 0;
+            out_ok = lb_ok != 0u;
         }
-        GLOBAL uint32_t *const out_items = sd.out_items;
+        GLOBAL uint32_t *const out_items = out_ok ? sd.out_items : nullptr;
 
         // ---- node state (all uniform)
         uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;            // data queue heads and tails

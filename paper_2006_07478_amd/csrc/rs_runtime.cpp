@@ -322,6 +322,19 @@ void plan_claims(Stream *s, uint32_t kind, bool ordered_out, uint32_t width, uin
     s->n_claims = (uint32_t)(((uint64_t)n_parents + s->B - 1) / s->B);
 }
 
+// Longest wait of one look-back step on a predecessor claim before the claim gives up and the
+// launch reports a device error: 2 s, far beyond any healthy wait (a predecessor publishes its
+// count within microseconds of starting).  RS_LOOKBACK_WAIT_US overrides it, so that tests can
+// drive the give-up path.
+uint32_t lookback_wait_us() {
+    if (const char *e = getenv("RS_LOOKBACK_WAIT_US")) {
+        char *end = nullptr;
+        const unsigned long v = strtoul(e, &end, 10);
+        if (end != e && v <= 0xFFFFFFFFul) return (uint32_t)v;
+    }
+    return 2000000u;
+}
+
 int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_id, bool probe,
                std::unique_ptr<Batch> &out) {
     std::unique_ptr<Batch> b(new Batch);
@@ -393,8 +406,9 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     a.collect_stats = (!probe && (p->d.flags & RS_COLLECT_STATS)) ? 1u : 0u;
     a.emit_outputs = (!probe && p->d.emit_outputs) ? 1u : 0u;
     a.bmax = bmax;
-    // the ordered output stream's look-back needs claims started in index order
+    // the ordered output stream's look-back needs claims taken in index order, from one counter
     a.n_parts = a.emit_outputs ? 1u : rs::CTL_NPART;
+    a.lb_wait_us = lookback_wait_us();
     out = std::move(b);
     return RS_OK;
 }

@@ -54,7 +54,7 @@ def run_dev(kind, strategy, offsets, elements, lengths=None, parent_param=None, 
         return p.read(sid), p.stats(sid)
 
 
-@pytest.mark.parametrize("L", [1, 64, 4096])
+@pytest.mark.parametrize("L", [1, 4, 16, 64, 256, 1024, 4096])
 def test_hash_expand_2p26(L):
     n = 1 << 26
     offsets = workloads.fixed_offsets(n, L)
@@ -82,6 +82,25 @@ def test_output_stream_2p26():
             got, out = p.read(sid), p.outputs(sid)
         check(got, ref, ("count", "sum", "min", "max"), f"2^26 outputs {SNAME[s]}")
         assert len(out) == len(ref.out) and np.array_equal(out, ref.out), f"2^26 output items {SNAME[s]}"
+
+
+def test_output_stream_2p26_L16():
+    """The ordered output stream at 2^26 elements in regions of 16, with the widths the autotuner
+    picks: claims of 255 parents, over 16000 of them, whose look-backs once waited on claims
+    owned by waves that had not started.  Claims now come from one ascending counter."""
+    n = 1 << 26
+    offsets = workloads.fixed_offsets(n, 16)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals, emit_outputs=True)
+    for s in ALL3:
+        say("2^26 output stream L 16", SNAME[s])
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=s, ensemble_width=0, emit_outputs=True) as p:
+            sid = p.push(dev(offsets), dev(vals), n_elements=n)
+            p.run()
+            say("   ensemble width", p.stats(sid).ensemble_width)
+            got, out = p.read(sid), p.outputs(sid)
+        check(got, ref, ("count", "sum", "min", "max"), f"2^26 L=16 outputs {SNAME[s]}")
+        assert len(out) == len(ref.out) and np.array_equal(out, ref.out), f"2^26 L=16 output items {SNAME[s]}"
 
 
 @pytest.mark.parametrize("mx", [16, 32, 2048])

@@ -29,6 +29,7 @@ def skip_unoffered(kind, strategy, width):
     if strategy not in strats(kind, width):
         pytest.skip("lane-resolved signals are offered for u32 kinds at widths up to 256")
 ALL = rs.RS_COUNT | rs.RS_SUM | rs.RS_MIN | rs.RS_MAX
+WIDTHS = [64, 128, 256, 512, 1024]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -465,9 +466,84 @@ def test_autotuned_pipeline_matches_oracle(tmp_path, monkeypatch):
                 p.run()
                 check(p.read(sid), ref, where=f"autotune L={L}")
                 st = p.stats(sid)
-                assert st.ensemble_width in (64, 128, 256, 512) and st.strategy in (0, 1)
+                assert st.ensemble_width in WIDTHS
+                assert st.strategy in strats(rs.RS_HASH_EXPAND, st.ensemble_width)
     lines = (tmp_path / "tune.txt").read_text().split("\n")
     assert len([l for l in lines if l.strip()]) == 2
+
+
+# ---- every configuration the autotuner can pick ----
+
+# Claims hold at most 255 parents, and a launch has at most 20 one-wave workgroups per compute
+# unit (5120 on 256 CUs), each taking two or more claims by index before any from a counter: with
+# regions of about 4 items, 2^22 parents make over 16000 claims, so every candidate's launch takes
+# claims both by index and from the counters.
+CAND_PARENTS = 1 << 22
+
+
+def candidate_inputs(kind):
+    if kind == rs.RS_TEXT_WORDS:
+        text, starts, lengths = workloads.text_workload(seed=31, total_bytes=40 << 20, mean_len=8.0, max_len=300)
+        return dict(offsets=starts, elements=text, lengths=lengths), oracle.run(
+            oracle.TEXT_WORDS, starts, text, lengths=lengths)
+    if kind == rs.RS_GRAPH_THRESH:
+        offsets, w, thr, _ = workloads.graph_workload(seed=32, n_vertices=CAND_PARENTS, n_edges=CAND_PARENTS * 4)
+        return dict(offsets=offsets, elements=w, parent_param=thr), oracle.run(
+            oracle.GRAPH_THRESH, offsets, w, parent_param=thr)
+    offsets = workloads.uniform_offsets(33, CAND_PARENTS, 8)
+    vals = workloads.hash_values(34, int(offsets[-1]))
+    ok = oracle.MODFILTER if kind == rs.RS_MODFILTER else oracle.HASH_EXPAND
+    param = (4, 0, 0, 0) if kind == rs.RS_MODFILTER else (0, 0, 0, 0)
+    return dict(offsets=offsets, elements=vals, param=param), oracle.run(ok, offsets, vals, param=param)
+
+
+_CAND = {}
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+@pytest.mark.parametrize("strategy", ALL3)
+@pytest.mark.parametrize("kind", [rs.RS_MODFILTER, rs.RS_HASH_EXPAND, rs.RS_TEXT_WORDS, rs.RS_GRAPH_THRESH])
+def test_every_autotune_candidate(kind, strategy, width):
+    """Each (kind, strategy, width) that RS_AUTO may select, against the oracle (§3.3: the SIMD rule
+    holds at any ensemble width)."""
+    skip_unoffered(kind, strategy, width)
+    if kind not in _CAND:
+        _CAND.clear()
+        _CAND[kind] = candidate_inputs(kind)
+    inp, ref = _CAND[kind]
+    say("candidate", kind, SNAME[strategy], width)
+    fields = rs.DEFAULT_FIELDS[kind]
+    got, _ = run_one(kind, strategy, width, inp["offsets"], inp["elements"], lengths=inp.get("lengths"),
+                     parent_param=inp.get("parent_param"), param=inp.get("param", (0, 0, 0, 0)), fields=fields,
+                     device=True)
+    check(got, ref, [n for n, bit, _ in rs.FIELDS if fields & bit], f"candidate {kind} {SNAME[strategy]} w={width}")
+
+
+def test_lookback_give_up_reports_a_device_error(monkeypatch):
+    """A look-back wait bounded at zero: a claim that finds a predecessor's count unpublished gives
+    up at once, writes no outputs and raises the launch's error flag.  Every wave still finishes:
+    the run either reports RS_EDEVICE or, when no claim had to wait, returns the exact stream.  A
+    pipeline with the normal bound then runs exactly."""
+    n = 1 << 22
+    offsets = workloads.fixed_offsets(n, 16)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals, emit_outputs=True)
+    say("look-back give-up")
+    monkeypatch.setenv("RS_LOOKBACK_WAIT_US", "0")
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256, emit_outputs=True) as p:
+        sid = p.push(offsets, vals)
+        try:
+            p.run()
+            check(p.read(sid), ref, where="zero bound")
+            assert np.array_equal(p.outputs(sid), ref.out)
+        except rs.RsError as e:
+            assert e.code == rs.RS_EDEVICE and "watchdog" in str(e)
+    monkeypatch.delenv("RS_LOOKBACK_WAIT_US")
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256, emit_outputs=True) as p:
+        sid = p.push(offsets, vals)
+        p.run()
+        check(p.read(sid), ref, where="normal bound")
+        assert np.array_equal(p.outputs(sid), ref.out)
 
 
 # ---- serving: continuous batching under an HBM budget ----
