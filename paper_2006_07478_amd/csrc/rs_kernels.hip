@@ -388,6 +388,9 @@ struct ClaimRegs {
     uint32_t off[R];   // CSR offsets[p0 + i] (i <= nb), or start of region p0 + i (i < nb)
     uint32_t len[R];   // length of region p0 + i (start+length streams)
     uint32_t ctx[R];   // per-parent context
+    uint32_t nb;                 // parents in the claim (uniform)
+    const uint8_t *elements;     // its stream's element array (uniform)
+    uint32_t n_elements;         // and that array's size
 };
 
 // ---------------------------------------------------------------- the pipeline kernel
@@ -414,7 +417,12 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     __shared__ uint32_t q1v[D1 + 64];
     __shared__ uint8_t q1a[KIND == RS_HASH_EXPAND ? D1 + 64 : 1];
     __shared__ uint8_t q1t[TAG ? D1 + 64 : 1];
-    __shared__ uint32_t q2v[HAS_E ? D2 + 64 : 1];
+    // fused firings (hash kind, below) use A's queue as a plain array: a leftover of under 64
+    // items, up to 3w children and two slots that a firing may write past its last child, then
+    // one dump slot (plus two) per lane for lanes without children
+    constexpr bool FUSE = (KIND == RS_HASH_EXPAND);
+    constexpr uint32_t FL = 3u * EW + 66u, FDUMP = FL;
+    __shared__ uint32_t q2v[HAS_E ? (FUSE ? (D2 + 64u > FL + 66u ? D2 + 64u : FL + 66u) : D2 + 64u) : 1];
     __shared__ uint8_t q2t[(HAS_E && TAG) ? D2 + 64 : 1];
     __shared__ uint32_t fsl[BYTES ? 1 : EW];   // staging slot for the enumerating node's next ensemble
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
@@ -466,15 +474,22 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         }
     };
     // this lane's share of the region table of claim gg (loads only; consumed a claim later)
+    // r.nb, r.elements and r.n_elements: the claim's parent count and its stream's element array
     auto load_claim = [&](uint32_t gg, ClaimRegs<R> &r) {
 #pragma unroll
         for (uint32_t q = 0; q < R; ++q) r.off[q] = r.len[q] = r.ctx[q] = 0;
+        r.nb = 0;
+        r.elements = nullptr;
+        r.n_elements = 0;
         if (gg >= a.total_claims) return;
         ensure_sd(stream_of(gg));
         const SDesc sd = load_sdesc(sdl);
         const uint32_t B = sd.B;
         const uint32_t p0 = (gg - sd.claim_begin) * B;
         const uint32_t nb = min(B, sd.n_parents - p0);
+        r.nb = nb;
+        r.elements = sd.elements;
+        r.n_elements = sd.n_elements;
 #pragma unroll
         for (uint32_t q = 0; q < R; ++q) {
             const uint32_t i = q * 64u + t;
@@ -563,6 +578,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     uint32_t g1 = take_claim();
     ClaimRegs<R> cur;
     load_claim(g, cur);
+    // claim whose first ensemble the staging slot receives, requested as the previous claim ended
+    // (u32 kinds), so that a claim does not start with a full memory round trip
+    uint32_t pf_g = 0xFFFFFFFFu;
 
     while (g < a.total_claims) {
         const uint32_t g_next = take_claim();   // the claim after g1
@@ -664,7 +682,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // the slot's contents into registers, so the copy overlaps whatever fires in between;
         // its completion is awaited explicitly (vmcnt) before the slot is read.  One slot, not
         // two: the LDS it saves buys more resident waves, which hide the latency better.
-        uint32_t spos = 0xFFFFFFFFu;   // position whose ensemble the slot holds or receives
+        uint32_t spos = pf_g == g ? vbeg : 0xFFFFFFFFu;   // position whose ensemble the slot holds or receives
         auto stage = [&](uint32_t pos) {
             if constexpr (!BYTES) {
                 spos = 0xFFFFFFFFu;
@@ -895,7 +913,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             (uint32_t)min(8ull * ((unsigned long long)(vend - vbeg) + nb) + 64ull, 0xFFFFFFFFull);
         uint32_t iters = 0;
 
-        stage(fpos);
+        if (spos != fpos) stage(fpos);
 
         // per-lane flush of the accumulator into region slot j (LDS atomics)
         auto flush_lane = [&](uint32_t j) {
@@ -1262,6 +1280,250 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             if constexpr (FULL) stat(ST_FULL + 0, 1u);
         };
 
+        // ---------------- fused firings (hash kind)
+        // A full ensemble that lies inside one region, met while the first queue and both signal
+        // queues are empty, needs neither a tag per item nor a signal to keep regions apart: F and
+        // E fire on it as one firing, each survivor writing its children straight into A's queue
+        // in serial order (no compaction of survivors into the first queue, no second read of
+        // them), and A then takes every whole 64-lane round of its queue.  During a run of such
+        // firings A's queue is a plain array from slot 0, its leftover of under 64 items moved to
+        // the front after each firing; the first queue's storage, empty meanwhile, is a second
+        // staging slot, so the next ensemble's copy is in flight while one is processed.  A region
+        // that ends between two ensembles closes as its end signal would close it: A takes the
+        // leftover (the signal's credit) and ends the region.  The run stops at the first ensemble
+        // that is not full or spans a region end, leaving the state the scheduler expects.
+        uint32_t spos2 = 0xFFFFFFFFu;   // position whose ensemble the second slot holds or receives
+        // region containing position pos (< vend), searching up from region j0 (start <= pos)
+        auto region_of = [&](uint32_t pos, uint32_t j0) -> uint32_t {
+            uint32_t r = j0;
+            while (uni(VT[r + 1u]) <= pos) ++r;
+            return r;
+        };
+        // whether the ensemble at fpos is full and inside one region
+        auto fuse_ok = [&]() -> bool {
+            if constexpr (!WALK) {
+                return fpos + EW <= rend;
+            } else {
+                if (fpos + EW > vend) return false;
+                const uint32_t r = region_of(fpos, TAG ? jlo : jb);
+                return uni(VT[r + 1u]) >= fpos + EW;
+            }
+        };
+        // A takes the n (< 64) items at the front of its queue: the last items of a region
+        auto fuse_drain = [&](uint32_t n) {
+            if (n) {
+                const uint32_t y = fmix32(q2v[t]);
+                if (out_items && t < n) out_items[out_rank + t] = y;
+                acc_add(acc, y, t < n);
+                a_items += n;
+                out_rank += n;
+                h2 += n;
+                stat(ST_FIRINGS + 2, 1u);
+                stat(ST_ITEMS + 2, n);
+            }
+        };
+        // A takes every whole 64-lane round of the avail items at the front of its queue (one
+        // region's children), w items per firing; returns how many it took
+        auto fuse_a = [&](uint32_t avail) -> uint32_t {
+            uint32_t base = 0;
+            while (avail - base >= EW) {
+                uint32_t y[V];
+#pragma unroll
+                for (int k = 0; k < V; ++k) y[k] = fmix32(q2v[base + (uint32_t)k * 64u + t]);
+                if (out_items) {
+#pragma unroll
+                    for (int k = 0; k < V; ++k) out_items[out_rank + (uint32_t)k * 64u + t] = y[k];
+                }
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    acc.sum += (unsigned long long)y[k];
+                    acc.mn = min(acc.mn, y[k]);
+                    acc.mx = max(acc.mx, y[k]);
+                }
+                acc.cnt += (uint32_t)V;
+                base += EW;
+                out_rank += EW;
+                stat(ST_FIRINGS + 2, 1u);
+                stat(ST_ITEMS + 2, EW);
+                stat(ST_FULL + 2, 1u);
+            }
+            const uint32_t nr = (avail - base) >> 6;   // whole rounds short of a full ensemble
+            if (nr) {
+#pragma unroll
+                for (int k = 0; k + 1 < V; ++k) {
+                    if ((uint32_t)k < nr) {
+                        const uint32_t y = fmix32(q2v[base + (uint32_t)k * 64u + t]);
+                        if (out_items) out_items[out_rank + (uint32_t)k * 64u + t] = y;
+                        acc.sum += (unsigned long long)y;
+                        acc.mn = min(acc.mn, y);
+                        acc.mx = max(acc.mx, y);
+                    }
+                }
+                acc.cnt += nr;
+                base += nr * 64u;
+                out_rank += nr * 64u;
+                stat(ST_FIRINGS + 2, 1u);
+                stat(ST_ITEMS + 2, nr * 64u);
+            }
+            a_items += base;
+            h2 += base;
+            return base;
+        };
+        // F and E as one firing on the full ensemble in src (a staging slot): survivor x writes
+        // its c children, as pre-images x ^ K(j+1), to A's queue from slot lt on, in serial
+        // order; returns the new end of A's queue.  Each lane writes its three candidate slots
+        // off+2, off+1, off in that order; a slot past a lane's last child belongs to a later
+        // item of the firing, whose own (later) write of a smaller child index lands on it, or
+        // lies past the firing's last child.  Lanes without children write their dump slots.
+        auto fuse_fe = [&](auto counting, const uint32_t *src, uint32_t lt) -> uint32_t {
+            constexpr bool COUNT = decltype(counting)::value;   // E's item count for the statistics
+            uint32_t x[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) x[k] = src[k * 64 + (int)t];
+            uint32_t run = lt, kept = 0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const uint32_t h = fmix32(x[k] ^ salt_key(0));
+                // survivors (bit 0) with an odd child count (bit 1), and with two or three (bit 2)
+                const uint64_t b0 = __ballot((h & 3u) == 3u);
+                const uint64_t b1 = __ballot((h & 5u) == 5u);
+                if constexpr (COUNT) kept += (uint32_t)__popcll(__ballot(h & 1u));
+                const uint32_t off = run + rank_below(b0) + 2u * rank_below(b1);
+                const uint32_t dst = pick(b0 | b1, off, FDUMP + t);
+                q2v[dst + 2u] = x[k] ^ salt_key(3u);
+                order();
+                q2v[dst + 1u] = x[k] ^ salt_key(2u);
+                order();
+                q2v[dst] = x[k] ^ salt_key(1u);
+                order();
+                run += (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1);
+            }
+            stat(ST_FIRINGS + 0, 1u);
+            stat(ST_ITEMS + 0, EW);
+            stat(ST_FULL + 0, 1u);
+            stat(ST_FIRINGS + 1, 1u);
+            stat(ST_ITEMS + 1, kept);
+            return uni(run);
+        };
+        // tags and lane-resolved signals: the region of the ensemble at fpos (< vend); when it is not
+        // the one A's accumulators hold, A takes the leftover lt of the old one and closes it (for
+        // lane-resolved signals the region ends before fpos then count as signalled and taken).
+        // Returns whether the ensemble is full and inside that region.
+        auto fuse_walk_region = [&](uint32_t &lt) -> bool {
+            const uint32_t r = region_of(fpos, TAG ? jlo : jb);
+            if (r != utag) {
+                fuse_drain(lt);
+                lt = 0;
+                flush_wave(utag);
+                utag = r;
+            }
+            if constexpr (LANES) {
+                if (r != jb) {
+                    stat(ST_SIGNALS + 0, r - jb);
+                    stat(ST_SIGNALS + 1, r - jb);
+                    stat(ST_SIGNALS + 2, r - jb);
+                    jb = r;
+                    bnext = uni(VT[r + 1u]);
+                }
+                ja = r;
+            } else {
+                if (r != jlo) {
+                    jlo = r;
+                    jnext = r + 1u < nb ? uni(VT[r + 1u]) : 0xFFFFFFFFu;
+                }
+            }
+            return uni(VT[r + 1u]) >= fpos + EW;
+        };
+        // a run of fused firings from fpos (the ensemble there is full and inside one region).  The
+        // loop tests the next ensemble at its bottom: a test at its top, which the entry has
+        // already passed, would give the loop a second entry.
+        auto fuse_run = [&]() {
+            // what A's queue holds (fewer than w items, none past a signal) goes first
+            if (h2 != t2) a_fire(BoolC<false>{}, t2 - h2);
+            h2w = t2w = 0;
+            uint32_t lt = 0;   // items at the front of A's queue
+            if constexpr (WALK) (void)fuse_walk_region(lt);
+            for (;;) {
+                // ---- the ensemble's slot, and the next ensemble's copy into the other slot (both
+                // slots' positions are updated by selects: a conditional store to one or the other
+                // would be merged into a store through a selected address, which keeps them out
+                // of registers)
+                const bool in2 = spos2 == fpos;
+                if (!in2 && spos != fpos) stage(fpos);
+                const uint32_t nx = fpos + EW;
+                const bool ahead = nx < vend;
+                if (ahead)
+                    lds_copy<V>(rsrc_words(elems + (size_t)nx * 4u, min(EW, vend - nx) * 4u),
+                                uni(in2 ? lds_addr(fsl) : lds_addr(q1v)), t * 4u);
+                const uint32_t npos = ahead ? nx : 0xFFFFFFFFu;
+                spos = in2 ? npos : spos;
+                spos2 = in2 ? spos2 : npos;
+                if (ahead) wait_vmem<V>(); else wait_vmem<0>();
+                // ---- F and E, then A on every whole round
+                const uint32_t *src = in2 ? q1v : fsl;
+                const uint32_t nt = collect ? fuse_fe(BoolC<true>{}, src, lt) : fuse_fe(BoolC<false>{}, src, lt);
+                t2 += nt - lt;
+                fpos += EW;
+                const uint32_t used = fuse_a(nt);
+                lt = nt - used;
+                if (lt && used) {   // the leftover to the front
+                    const uint32_t v = q2v[used + t];
+                    order();
+                    if (t < lt) q2v[t] = v;
+                    order();
+                }
+                // ---- region ends at fpos, and whether the next ensemble can be fused
+                if constexpr (!WALK) {
+                    if (fpos == rend) {
+                        // region ja ends: A takes the items before its signal, then ends it
+                        fuse_drain(lt);
+                        lt = 0;
+                        if (a_items) {
+                            const Acc r = wave_reduce(acc);
+                            if (t == 0) {
+                                s_cnt[ja] = r.cnt;
+                                s_sum[ja] = r.sum;
+                                s_min[ja] = r.mn;
+                                s_max[ja] = r.mx;
+                            }
+                            acc_reset(acc);
+                            a_items = 0;
+                        }
+                        // the region's signal, and those of the empty regions after it
+                        do {
+                            ++fj;
+                            ++ej;
+                            ++ja;
+                            stat(ST_SIGNALS + 0, 1u);
+                            stat(ST_SIGNALS + 1, 1u);
+                            stat(ST_SIGNALS + 2, 1u);
+                        } while (fj < nb && uni(VT[fj + 1u]) == fpos);
+                        fdone = fj == nb;   // (an unconditional store, as for the slots above)
+                        if (fdone) break;
+                        rend = uni(VT[fj + 1u]);
+                    }
+                    if (fpos + EW > rend) break;
+                } else {
+                    if (fpos + EW > vend) break;
+                    if (!fuse_walk_region(lt)) break;
+                }
+            }
+            // A's queue holds the leftover in slots [0, lt) for the scheduler
+            t2w = lt;
+            if constexpr (TAG) {
+                if (t < lt) q2t[t] = (uint8_t)utag;
+            }
+            if constexpr (TAG) {
+                fdone = (fpos == vend);
+            } else if constexpr (LANES) {
+                fdone = (fpos == vend && jb == nb);
+            }
+            if (spos2 != 0xFFFFFFFFu) {   // no copy into the first queue's storage outlives the run
+                wait_vmem<0>();
+                spos2 = 0xFFFFFFFFu;
+            }
+        };
+
         for (;;) {
             if (++iters > iter_cap) {
                 failed = true;
@@ -1385,6 +1647,17 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     }
                 }
             }
+            // ---------------- F and E fused, then A (hash kind, a full ensemble inside one region)
+            if constexpr (FUSE) {
+                if (!fdone && h1 == t1 && sh1 == st1 && sh2 == st2 && fuse_ok()) {
+                    fuse_run();
+                    // the queue state after the run is opaque to the compiler: threading what it
+                    // knows of it into the next pass would merge the scheduler loop into the claim
+                    // loop and shuffle its state at every join
+                    asm volatile("" : "+s"(h1), "+s"(sh1), "+s"(sh2));
+                    continue;
+                }
+            }
             // ---------------- F
             if constexpr (LANES) {
                 if (!fdone) {
@@ -1479,6 +1752,26 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         g = g1;
         g1 = g_next;
         cur = nxt;
+        // the next claim's first ensemble, when its range lies inside its element array (a
+        // malformed claim is caught before any of its own reads).  Requested after the copy of the
+        // next claim's region table above, which waits for that table's loads and would wait for
+        // this copy too if it came first.
+        pf_g = 0xFFFFFFFFu;
+        if constexpr (!BYTES) {
+            if (g < a.total_claims) {
+                const uint32_t nnb = cur.nb;
+                const uint32_t vb = uni(__builtin_amdgcn_readlane(cur.off[0], 0));
+                uint32_t ve = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < R; ++q)
+                    if (q == (nnb >> 6)) ve = uni(__builtin_amdgcn_readlane(cur.off[q], nnb & 63u));
+                if (vb < ve && ve <= cur.n_elements) {
+                    lds_copy<V>(rsrc_words(cur.elements + (size_t)vb * 4u, min(EW, ve - vb) * 4u), uni(lds_addr(fsl)),
+                                t * 4u);
+                    pf_g = g;
+                }
+            }
+        }
     }
 }
 

@@ -308,15 +308,18 @@ hipStream_t lane_of(rs_pipeline *p, uint64_t batch_id) {
 // ---------------------------------------------------------------- batches
 
 // Claim size: about 16 ensembles of elements per claim, at most claim_parents_max(w)
-// parents, at least one parent.  An ordered output stream over u32 elements takes about 32 when
-// the stream still makes at least 2048 such claims (8 per compute unit): its claims start in
-// index order and each waits on its predecessor's output offset, so fewer, larger claims
-// shorten that chain.  Text lines, whose lengths vary widely, and streams with fewer claims keep
-// 16.
+// parents, at least one parent.  Over u32 elements a claim takes about 32 ensembles when the
+// stream still makes enough such claims: at least 8192 (two for each of the about 4096 waves a
+// launch keeps resident) for aggregation, where each claim's fixed cost (its region table, its
+// records, its first copy) then falls on twice the elements; at least 2048 (8 per compute unit)
+// for an ordered output stream, whose claims start in index order and each wait on its
+// predecessor's output offset, so that fewer, larger claims shorten that chain.  Text lines,
+// whose lengths vary widely, and smaller streams keep 16.
 void plan_claims(Stream *s, uint32_t kind, bool ordered_out, uint32_t width, uint32_t n_parents) {
     const double bmax = rs::claim_parents_max(width);
-    const bool big = ordered_out && kind != RS_TEXT_WORDS && s->mean_len > 0 &&
-                     (double)n_parents * s->mean_len >= 2048.0 * 32.0 * width;
+    const double min_claims = ordered_out ? 2048.0 : 8192.0;
+    const bool big = kind != RS_TEXT_WORDS && s->mean_len > 0 &&
+                     (double)n_parents * s->mean_len >= min_claims * 32.0 * width;
     const double b = s->mean_len > 0 ? (big ? 32.0 : 16.0) * width / s->mean_len : bmax;
     s->B = (uint32_t)std::max(1.0, std::min(bmax, b));
     s->n_claims = (uint32_t)(((uint64_t)n_parents + s->B - 1) / s->B);
