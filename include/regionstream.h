@@ -264,6 +264,27 @@ typedef struct {
 int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view *out, rs_request_timing *timing,
           uint32_t flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): run(), for n_streams (1..16) device-resident streams
+ * in one persistent launch, with no allocation of any kind.  The library's device state for the
+ * call (control block, stream table, statistics: about 12 KB) lives in one static array per device,
+ * held until the process ends; the caller passes inputs and outputs.
+ *   d          as for pipeline_create, with an explicit strategy (not RS_AUTO) and ensemble width,
+ *              emit_outputs = 0 and queue_depth 0 or 2 * ensemble_width
+ *   streams    n_streams stream descriptions, mem = RS_MEM_DEVICE (borrowed until the launch ends)
+ *   out        n_streams destinations: device arrays [n_parents] of every field in agg_fields
+ *   hip_stream HIP stream the launch is enqueued on (NULL: the default stream)
+ *   flags      RS_RUN_SYNC: wait and report device errors (watchdog, malformed regions);
+ *              RS_RUN_ASYNC: return after enqueueing, device errors are not reported
+ * Calls on one device share its array: calls that overlap on a device (different host threads
+ * or HIP streams without ordering) race and give wrong results.  Each call clears what must start
+ * at zero.  Results are bit-identical to pipeline_create/stream_push/run/read_aggregates with the
+ * same strategy and width.
+ * Errors: RS_EINVAL (bad description, more than 16 streams, host memory, NULL destination,
+ * malformed regions), RS_EDEVICE. */
+int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams, uint32_t n_streams,
+                rs_agg_view *out, void *hip_stream, uint32_t flags);
+
 /* Measurement aid: copy `bytes` (a multiple of 16) from src to dst, both 16-byte aligned device
  * memory, with a plain grid-stride copy kernel enqueued on hip_stream (NULL: the default stream).
  * It is the achievable-bandwidth reference beside the pipeline kernels and the known-size copy

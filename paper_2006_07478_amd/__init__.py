@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "RS_OK", -1: "RS_EINVAL", -2: "RS_ENOMEM", -3: "RS_EDEVICE", 
 
 ABI_FUNCTIONS = ["pipeline_create", "pipeline_set_stream", "stream_push", "run", "run_again",
                  "read_aggregates", "read_outputs", "rs_stats", "kernel_times", "stream_release", "serve", "hbm_probe",
-                 "pipeline_destroy", "rs_last_error"]
+                 "run_noalloc", "pipeline_destroy", "rs_last_error"]
+NOALLOC_MAX_STREAMS = 16
 
 
 class RsError(RuntimeError):
@@ -98,6 +99,8 @@ def lib():
                             ctypes.POINTER(rs_request_timing), u32]
         L.pipeline_destroy.argtypes = [vp]
         L.hbm_probe.argtypes = [vp, vp, u64, vp]
+        L.run_noalloc.argtypes = [ctypes.POINTER(rs_pipeline_desc), ctypes.POINTER(rs_stream_desc), u32,
+                                  ctypes.POINTER(rs_agg_view), vp, u32]
         L.rs_last_error.restype = ctypes.c_char_p
         L.rs_last_error.argtypes = []
         for name in ABI_FUNCTIONS[:-1]:
@@ -175,6 +178,12 @@ def serve(p, reqs, n, out, timing, flags=0):
 
 def hbm_probe(src_ptr, dst_ptr, nbytes, hip_stream=None):
     return _check(lib().hbm_probe(src_ptr, dst_ptr, nbytes, hip_stream))
+
+
+def run_noalloc(desc, streams, n_streams, out, hip_stream=None, flags=RS_RUN_SYNC):
+    """streams: ctypes array of rs_stream_desc (device memory); out: ctypes array of rs_agg_view
+    (device pointers)."""
+    return _check(lib().run_noalloc(ctypes.byref(desc), streams, n_streams, out, hip_stream, flags))
 
 
 def pipeline_destroy(p):

@@ -63,6 +63,19 @@ struct LaunchArgs {
     uint32_t pad;
 };
 
+// The no-allocation entry point (run_noalloc) keeps its device state in one static array of
+// the kernel file: the control block, a table of at most NOALLOC_MAX_STREAMS streams and their
+// statistics.  The table reaches the device as a kernel argument (no host staging buffer).
+constexpr uint32_t NOALLOC_MAX_STREAMS = 16;
+constexpr uint32_t NOALLOC_CTL_OFF = 0;
+constexpr uint32_t NOALLOC_TABLE_OFF = 8448;   // CTL_WORDS * 4, a multiple of 256
+constexpr uint32_t NOALLOC_STATS_OFF = NOALLOC_TABLE_OFF + NOALLOC_MAX_STREAMS * 128;
+constexpr uint32_t NOALLOC_SCRATCH_BYTES = NOALLOC_STATS_OFF + NOALLOC_MAX_STREAMS * 16 * 8;
+struct NoallocTable {
+    StreamDev s[NOALLOC_MAX_STREAMS];
+    uint32_t n;
+};
+
 // Kernel entry points (defined in rs_kernels.hip).
 // Lanes per workgroup of the kernel for ensemble width w (w = lanes * items per lane).
 uint32_t lanes_of(uint32_t ensemble_width);
@@ -77,6 +90,12 @@ int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t bma
 // Bytes of per-claim LDS (region table and aggregate slots) for claims of up to bmax parents.
 uint32_t dyn_lds_bytes(uint32_t kind, uint32_t bmax);
 int launch_probe_copy(const void *src, void *dst, unsigned long long bytes, uint32_t n_cu, void *stream);
+// Device address of the no-allocation scratch array on the current device (looked up once per
+// device with hipGetSymbolAddress; the array itself is file-scope in rs_kernels.hip).
+int noalloc_scratch(void **out);
+// Clears the control block and the statistics in the scratch array at base and writes the stream
+// table there, on stream.
+int launch_noalloc_init(void *base, const NoallocTable &tab, void *stream);
 
 
 }  // namespace rs

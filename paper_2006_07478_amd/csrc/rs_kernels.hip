@@ -40,6 +40,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "rs_internal.h"
 #include "../../include/regionstream.h"
 
@@ -1845,6 +1847,52 @@ __global__ void __launch_bounds__(256) probe_copy(const uint4 *__restrict__ src,
 int launch_probe_copy(const void *src, void *dst, unsigned long long bytes, uint32_t n_cu, void *stream) {
     hipLaunchKernelGGL(probe_copy, dim3(n_cu * 4), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src,
                        (uint4 *)dst, bytes / 16);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------- no-allocation scratch
+
+static_assert(CTL_WORDS * 4u == NOALLOC_TABLE_OFF, "control block fills the scratch's first part");
+static_assert(sizeof(StreamDev) <= 128u && sizeof(NoallocTable) <= 4096u, "table fits its part and a kernel argument");
+
+// Device state of the no-allocation entry point: control block, stream table, statistics.  Each
+// device holds its own copy until the process ends; calls on one device share it.  Host code
+// never uses this name as an address: it is looked up per device below.
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+int noalloc_scratch(void **out) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= 64) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the current device's copy
+        if (e != hipSuccess) return (int)e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return (int)hipSuccess;
+}
+
+// Clears the control block and the statistics words, then writes the stream table (a kernel, not
+// a memset or a copy from host memory, so that the call allocates nothing and can be captured).
+__global__ void __launch_bounds__(64) rs_noalloc_init(uint8_t *base, NoallocTable tab) {
+    const uint32_t t = threadIdx.x;
+    uint32_t *ctl = (uint32_t *)(base + NOALLOC_CTL_OFF);
+    for (uint32_t i = t; i < CTL_WORDS; i += 64u) ctl[i] = 0u;
+    unsigned long long *st = (unsigned long long *)(base + NOALLOC_STATS_OFF);
+    for (uint32_t i = t; i < NOALLOC_MAX_STREAMS * ST_WORDS; i += 64u) st[i] = 0ull;
+    uint32_t *dst = (uint32_t *)(base + NOALLOC_TABLE_OFF);
+    const uint32_t *src = (const uint32_t *)tab.s;
+    for (uint32_t i = t; i < tab.n * (uint32_t)(sizeof(StreamDev) / 4u); i += 64u) dst[i] = src[i];
+}
+
+int launch_noalloc_init(void *base, const NoallocTable &tab, void *stream) {
+    hipLaunchKernelGGL(rs_noalloc_init, dim3(1), dim3(64), 0, (hipStream_t)stream, (uint8_t *)base, tab);
     return (int)hipGetLastError();
 }
 

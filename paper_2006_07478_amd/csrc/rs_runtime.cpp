@@ -37,17 +37,18 @@
 
 namespace {
 
-thread_local std::string g_err;
+// message of the last failure on this thread (a fixed buffer: recording an error allocates nothing)
+thread_local char g_err[512];
 
 int fail(int code, const char *fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
+
+void clear_error() { g_err[0] = '\0'; }
 
 #define HIP_OR(expr, code)                                                                   \
     do {                                                                                     \
@@ -315,14 +316,19 @@ hipStream_t lane_of(rs_pipeline *p, uint64_t batch_id) {
 // for an ordered output stream, whose claims start in index order and each wait on its
 // predecessor's output offset, so that fewer, larger claims shorten that chain.  Text lines,
 // whose lengths vary widely, and smaller streams keep 16.
-void plan_claims(Stream *s, uint32_t kind, bool ordered_out, uint32_t width, uint32_t n_parents) {
+void claim_plan(uint32_t kind, bool ordered_out, uint32_t width, uint32_t n_parents, double mean_len, uint32_t *B,
+                uint32_t *n_claims) {
     const double bmax = rs::claim_parents_max(width);
     const double min_claims = ordered_out ? 2048.0 : 8192.0;
-    const bool big = kind != RS_TEXT_WORDS && s->mean_len > 0 &&
-                     (double)n_parents * s->mean_len >= min_claims * 32.0 * width;
-    const double b = s->mean_len > 0 ? (big ? 32.0 : 16.0) * width / s->mean_len : bmax;
-    s->B = (uint32_t)std::max(1.0, std::min(bmax, b));
-    s->n_claims = (uint32_t)(((uint64_t)n_parents + s->B - 1) / s->B);
+    const bool big = kind != RS_TEXT_WORDS && mean_len > 0 &&
+                     (double)n_parents * mean_len >= min_claims * 32.0 * width;
+    const double b = mean_len > 0 ? (big ? 32.0 : 16.0) * width / mean_len : bmax;
+    *B = (uint32_t)std::max(1.0, std::min(bmax, b));
+    *n_claims = (uint32_t)(((uint64_t)n_parents + *B - 1) / *B);
+}
+
+void plan_claims(Stream *s, uint32_t kind, bool ordered_out, uint32_t width, uint32_t n_parents) {
+    claim_plan(kind, ordered_out, width, n_parents, s->mean_len, &s->B, &s->n_claims);
 }
 
 // Longest wait of one look-back step on a predecessor claim before the claim gives up and the
@@ -603,10 +609,10 @@ void release(rs_pipeline *p, Stream *s) {
 
 // ------------------------------------------------------------------------------ ABI
 
-RS_API const char *rs_last_error(void) { return g_err.c_str(); }
+RS_API const char *rs_last_error(void) { return g_err; }
 
 RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
-    g_err.clear();
+    clear_error();
     if (!d || !out) return fail(RS_EINVAL, "NULL argument");
     *out = nullptr;
     if (d->abi_version != RS_ABI_VERSION)
@@ -658,7 +664,7 @@ RS_API int pipeline_set_stream(rs_pipeline *p, void *hip_stream) {
 }
 
 RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id) {
-    g_err.clear();
+    clear_error();
     if (!p || !stream_id) return fail(RS_EINVAL, "NULL argument");
     int rc = check_stream(p, s);
     if (rc) return rc;
@@ -825,7 +831,7 @@ std::vector<Stream *> admissible(rs_pipeline *p, const std::vector<Stream *> &ca
 }  // namespace
 
 RS_API int run(rs_pipeline *p, uint32_t flags) {
-    g_err.clear();
+    clear_error();
     if (!p) return fail(RS_EINVAL, "NULL pipeline");
     if (flags & ~3u) return fail(RS_EINVAL, "unknown run flags");
     std::vector<Stream *> cands;
@@ -834,7 +840,7 @@ RS_API int run(rs_pipeline *p, uint32_t flags) {
 }
 
 RS_API int run_again(rs_pipeline *p, uint32_t flags) {
-    g_err.clear();
+    clear_error();
     if (!p) return fail(RS_EINVAL, "NULL pipeline");
     if (flags & ~1u) return fail(RS_EINVAL, "unknown run flags");
     auto it = p->batches.find(p->last_batch);
@@ -856,7 +862,7 @@ RS_API int run_again(rs_pipeline *p, uint32_t flags) {
 }
 
 RS_API int read_aggregates(rs_pipeline *p, uint64_t stream_id, rs_agg_view *out, uint32_t flags) {
-    g_err.clear();
+    clear_error();
     if (!p || !out) return fail(RS_EINVAL, "NULL argument");
     if (flags & ~7u) return fail(RS_EINVAL, "unknown read flags");
     Stream *s = nullptr;
@@ -886,7 +892,7 @@ RS_API int read_aggregates(rs_pipeline *p, uint64_t stream_id, rs_agg_view *out,
 
 RS_API int read_outputs(rs_pipeline *p, uint64_t stream_id, uint32_t *out, uint64_t cap, uint64_t *n_out,
                         uint32_t flags) {
-    g_err.clear();
+    clear_error();
     if (!p || !n_out) return fail(RS_EINVAL, "NULL argument");
     if (!p->d.emit_outputs) return fail(RS_EINVAL, "pipeline was created without emit_outputs");
     Stream *s = nullptr;
@@ -912,7 +918,7 @@ RS_API int read_outputs(rs_pipeline *p, uint64_t stream_id, uint32_t *out, uint6
 }
 
 RS_API int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out) {
-    g_err.clear();
+    clear_error();
     if (!p || !out) return fail(RS_EINVAL, "NULL argument");
     Stream *s = nullptr;
     int rc = find_done(p, stream_id, 0, &s);
@@ -942,7 +948,7 @@ RS_API int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out) {
 }
 
 RS_API int stream_release(rs_pipeline *p, uint64_t stream_id) {
-    g_err.clear();
+    clear_error();
     if (!p) return fail(RS_EINVAL, "NULL pipeline");
     auto it = p->streams.find(stream_id);
     if (it == p->streams.end()) return fail(RS_ENOTFOUND, "unknown stream id %llu", (unsigned long long)stream_id);
@@ -959,7 +965,7 @@ RS_API int stream_release(rs_pipeline *p, uint64_t stream_id) {
 
 RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view *out, rs_request_timing *timing,
                  uint32_t flags) {
-    g_err.clear();
+    clear_error();
     if (!p || (n && (!reqs || !timing))) return fail(RS_EINVAL, "NULL argument");
     if (flags & ~RS_RUN_PER_STREAM) return fail(RS_EINVAL, "unknown serve flags");
     for (uint64_t i = 1; i < n; ++i)
@@ -1077,8 +1083,117 @@ RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view
     return last_rc == RS_OK ? RS_OK : fail(last_rc, "some requests failed (see timing[].status)");
 }
 
+RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams, uint32_t n_streams,
+                       rs_agg_view *out, void *hip_stream, uint32_t flags) {
+    clear_error();
+    // ---- everything is checked before the device is touched
+    if (!d || !streams || !out) return fail(RS_EINVAL, "NULL argument");
+    if (flags & ~RS_RUN_ASYNC) return fail(RS_EINVAL, "unknown run flags");
+    if (n_streams == 0 || n_streams > rs::NOALLOC_MAX_STREAMS)
+        return fail(RS_EINVAL, "run_noalloc takes 1 to %u streams per call (got %u)", rs::NOALLOC_MAX_STREAMS, n_streams);
+    if (d->abi_version != RS_ABI_VERSION) return fail(RS_EINVAL, "abi_version %u, library is %u", d->abi_version, RS_ABI_VERSION);
+    if (d->kind < RS_MODFILTER || d->kind > RS_GRAPH_THRESH) return fail(RS_EINVAL, "unknown kind %u", d->kind);
+    if (d->strategy == RS_AUTO || !rs::kernel_supported(d->kind, d->strategy, d->ensemble_width))
+        return fail(RS_EINVAL, "run_noalloc needs an explicit strategy and ensemble width the kernels offer "
+                               "(autotuning allocates)");
+    if (d->agg_fields == 0 || (d->agg_fields & ~15u))
+        return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX");
+    if (d->emit_outputs) return fail(RS_EINVAL, "run_noalloc does not produce the ordered output stream");
+    if (d->queue_depth && d->queue_depth != 2 * d->ensemble_width)
+        return fail(RS_EINVAL, "queue_depth %u: this build sizes queues at 2 * ensemble_width", d->queue_depth);
+    if (d->kind == RS_MODFILTER && d->param[0] != 0 && d->param[1] >= d->param[0])
+        return fail(RS_EINVAL, "residue must be smaller than the modulus");
+    const bool text = d->kind == RS_TEXT_WORDS;
+    const uint32_t eb = elem_bytes_of(d->kind);
+    rs::NoallocTable tab;
+    std::memset(&tab, 0, sizeof tab);
+    tab.n = n_streams;
+    uint64_t claims = 0;
+    uint32_t bmax = 1;
+    for (uint32_t i = 0; i < n_streams; ++i) {
+        const rs_stream_desc &s = streams[i];
+        if (s.mem != RS_MEM_DEVICE) return fail(RS_EINVAL, "stream %u: run_noalloc takes device memory only", i);
+        if (s.elem_bytes != eb) return fail(RS_EINVAL, "stream %u: elem_bytes must be %u for this kind", i, eb);
+        if (s.n_parents >= (1ull << 32)) return fail(RS_EINVAL, "stream %u: n_parents must be < 2^32", i);
+        if (s.n_elements * eb > 0xFFFFFF00ull) return fail(RS_EINVAL, "stream %u exceeds the 4 GiB addressing limit", i);
+        if (s.n_parents && !s.offsets) return fail(RS_EINVAL, "stream %u: offsets is NULL", i);
+        if (s.n_elements && !s.elements) return fail(RS_EINVAL, "stream %u: elements is NULL", i);
+        if (s.n_parents && text != (s.lengths != nullptr))
+            return fail(RS_EINVAL, text ? "stream %u: text streams need starts + lengths" : "stream %u: u32 streams need CSR offsets", i);
+        if (d->kind == RS_GRAPH_THRESH && s.n_parents && !s.parent_param)
+            return fail(RS_EINVAL, "stream %u: RS_GRAPH_THRESH needs parent_param", i);
+        if ((uintptr_t)s.elements & 15u) return fail(RS_EINVAL, "stream %u: element array must be 16-byte aligned", i);
+        const rs_agg_view &o = out[i];
+        if (s.n_parents && (((d->agg_fields & RS_COUNT) && !o.count) || ((d->agg_fields & RS_SUM) && !o.sum) ||
+                            ((d->agg_fields & RS_MIN) && !o.min) || ((d->agg_fields & RS_MAX) && !o.max)))
+            return fail(RS_EINVAL, "stream %u: a destination of a requested field is NULL", i);
+        uint32_t B = 1, nc = 0;
+        const uint32_t P = (uint32_t)s.n_parents;
+        claim_plan(d->kind, false, d->ensemble_width, P, P ? (double)s.n_elements / P : 0.0, &B, &nc);
+        rs::StreamDev &e = tab.s[i];
+        e.elements = s.elements;
+        e.offsets = s.offsets;
+        e.lengths = s.lengths;
+        e.pparam = s.parent_param;
+        e.agg_count = o.count;
+        e.agg_sum = (unsigned long long *)o.sum;
+        e.agg_min = o.min;
+        e.agg_max = o.max;
+        e.n_parents = P;
+        e.n_elements = (uint32_t)s.n_elements;
+        e.parents_per_claim = B;
+        e.n_claims = nc;
+        e.claim_begin = (uint32_t)claims;
+        claims += nc;
+        bmax = std::max(bmax, std::min(B, P));
+    }
+    if (claims >= (1ull << 32) - (1ull << 20)) return fail(RS_EINVAL, "too many claims in one call");
+    // ---- device state: the scratch array of the current device (no allocation)
+    void *base = nullptr;
+    int hrc = rs::noalloc_scratch(&base);
+    if (hrc) return fail(RS_EDEVICE, "scratch lookup: %s", hipGetErrorString((hipError_t)hrc));
+    for (uint32_t i = 0; i < n_streams; ++i)
+        tab.s[i].stats = (unsigned long long *)((uint8_t *)base + rs::NOALLOC_STATS_OFF) + i * rs::ST_WORDS;
+    int dev = 0, n_cu = 0;
+    HIP_OR(hipGetDevice(&dev), RS_EDEVICE);
+    HIP_OR(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), RS_EDEVICE);
+    const int per_cu = rs::blocks_per_cu(d->kind, d->strategy, d->ensemble_width, bmax);
+    if (per_cu <= 0) return fail(RS_EDEVICE, "kernel does not fit on a compute unit");
+    rs::LaunchArgs a{};
+    a.streams = (const rs::StreamDev *)((uint8_t *)base + rs::NOALLOC_TABLE_OFF);
+    a.ctl = (uint32_t *)((uint8_t *)base + rs::NOALLOC_CTL_OFF);
+    a.n_streams = n_streams;
+    a.total_claims = (uint32_t)claims;
+    std::memcpy(a.param, d->param, sizeof a.param);
+    a.agg_fields = d->agg_fields;
+    a.collect_stats = 0;
+    a.emit_outputs = 0;
+    a.bmax = bmax;
+    a.n_parts = rs::CTL_NPART;
+    a.lb_wait_us = lookback_wait_us();
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((claims + 1) / 2, (uint64_t)per_cu * n_cu));
+    hrc = rs::launch_noalloc_init(base, tab, hip_stream);
+    if (hrc) return fail(RS_EDEVICE, "init launch: %s", hipGetErrorString((hipError_t)hrc));
+    if (claims) {
+        hrc = rs::launch_pipeline(d->kind, d->strategy, d->ensemble_width, a, grid, hip_stream);
+        if (hrc) return fail(RS_EDEVICE, "kernel launch failed: %s", hipGetErrorString((hipError_t)hrc));
+    }
+    if (flags & RS_RUN_ASYNC) return RS_OK;
+    // ---- synchronous call: the device's verdict
+    HIP_OR(hipStreamSynchronize((hipStream_t)hip_stream), RS_EDEVICE);
+    uint32_t err = 0;
+    HIP_OR(hipMemcpy(&err, (uint8_t *)base + rs::NOALLOC_CTL_OFF + 4 * rs::CTL_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
+    if (err) return fail(RS_EDEVICE, "the device scheduler stopped a claim (watchdog or internal check)");
+    for (uint32_t i = 0; i < n_streams; ++i) {
+        uint32_t bad = 0;
+        HIP_OR(hipMemcpy(&bad, tab.s[i].stats + rs::ST_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
+        if (bad) return fail(RS_EINVAL, "stream %u has malformed regions (out of order or past n_elements)", i);
+    }
+    return RS_OK;
+}
+
 RS_API int hbm_probe(const void *src, void *dst, uint64_t bytes, void *hip_stream) {
-    g_err.clear();
+    clear_error();
     if (!src || !dst) return fail(RS_EINVAL, "NULL argument");
     if (((uintptr_t)src | (uintptr_t)dst | bytes) & 15u) return fail(RS_EINVAL, "pointers and size must be 16-byte multiples");
     int dev = 0;
@@ -1091,7 +1206,7 @@ RS_API int hbm_probe(const void *src, void *dst, uint64_t bytes, void *hip_strea
 }
 
 RS_API int kernel_times(rs_pipeline *p, float *ms, uint32_t cap, uint32_t *n) {
-    g_err.clear();
+    clear_error();
     if (!p || !n) return fail(RS_EINVAL, "NULL argument");
     if (!(p->d.flags & RS_TIME_KERNEL)) return fail(RS_EINVAL, "the pipeline was created without RS_TIME_KERNEL");
     if (cap && !ms) return fail(RS_EINVAL, "NULL ms with cap > 0");

@@ -77,3 +77,26 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(rs, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         rs.lib()
+
+
+def test_noalloc_rejects_more_streams_than_its_scratch_holds():
+    """The no-allocation entry point refuses a call beyond its fixed table (16 streams) before
+    touching any device."""
+    d = _desc()
+    n = rs.NOALLOC_MAX_STREAMS + 1
+    sd = (rs.rs_stream_desc * n)()
+    ov = (rs.rs_agg_view * n)()
+    with pytest.raises(rs.RsError) as e:
+        rs.run_noalloc(d, sd, n, ov)
+    assert e.value.code == rs.RS_EINVAL and "16 streams" in str(e.value)
+
+
+def test_noalloc_needs_an_explicit_configuration():
+    """Autotuning allocates, so the no-allocation entry point takes an explicit strategy and width."""
+    for kw in ({"strategy": rs.RS_AUTO}, {"ensemble_width": 0}, {"emit_outputs": 1}):
+        d = _desc(**kw)
+        sd = (rs.rs_stream_desc * 1)()
+        ov = (rs.rs_agg_view * 1)()
+        with pytest.raises(rs.RsError) as e:
+            rs.run_noalloc(d, sd, 1, ov)
+        assert e.value.code == rs.RS_EINVAL
