@@ -116,40 +116,65 @@ __device__ __forceinline__ u32x4 rsrc_words(const void *base, uint32_t bytes) {
 
 #define RS_LDSCOPY(off) "buffer_load_dword %[v], %[r], 0 offen offset:" #off " lds\n\t"
 #define RS_LDSCOPY4(a, b, c, d) RS_LDSCOPY(a) RS_LDSCOPY(b) RS_LDSCOPY(c) RS_LDSCOPY(d)
+#define RS_LDSCOPY16(off) "buffer_load_dwordx4 %[v], %[r], 0 offen offset:" #off " lds\n\t"
 #define RS_LDSCOPY_BEGIN "s_nop 2\n\ts_mov_b32 %[s], m0\n\ts_mov_b32 m0, %[m]\n\ts_nop 0\n\t"
 
-// Copies V rounds of 64 words from the buffer to LDS at lds_base: round k moves word
-// k*64 + lane (the immediate offset advances both addresses).  The copy is written as asm so
-// that the compiler neither orders other LDS accesses behind it nor waits for it: its
-// completion is awaited explicitly (vmcnt) before the words are read.  m0 holds the LDS base
-// and is restored afterwards.  The compiler's hazard checks do not look inside asm, so the
-// wait states are part of it: five between a vector write of the descriptor's scalar
-// registers (a readfirstlane just before) and the loads that read them, and one between the
-// write of m0 and a load into LDS.
+// Vector-memory instructions a full ensemble's copy takes (lds_copy below).
 template <int V>
-__device__ __forceinline__ void lds_copy(u32x4 r, uint32_t lds_base, uint32_t voff) {
+constexpr int copy_ops() {
+    return V == 1 ? 1 : V == 2 ? 2 : V / 4;
+}
+
+// Copies one ensemble's words from the buffer to LDS at lds_base, word i to word i: a full
+// ensemble of V >= 4 rounds with one 16-byte load per lane per kilobyte, anything else with one
+// 4-byte load per lane per 64 words (the immediate offset advances both addresses).  A partial
+// ensemble's range ends inside a 16-byte group, and its 4-byte loads are checked against the
+// range one word each.  Written as asm so that the compiler neither orders other LDS accesses
+// behind the copy nor waits for it: its completion is awaited explicitly (vmcnt) before the words
+// are read; a partial copy takes more instructions than copy_ops<V>(), so a wait sized for a full
+// one waits for at least as much.  m0 holds the LDS base and is restored afterwards.  The
+// compiler's hazard checks do not look inside asm, so the wait states are part of it: five
+// between a vector write of the descriptor's scalar registers (a readfirstlane just before) and
+// the loads that read them, and one between the write of m0 and a load into LDS.
+template <int V>
+__device__ __forceinline__ void lds_copy(u32x4 r, uint32_t lds_base, uint32_t lane, bool full) {
     uint32_t save;
+    if constexpr (V >= 4) {
+        if (full) {
+            if constexpr (V == 4) {
+                asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY16(0) "s_mov_b32 m0, %[s]"
+                             : [s] "=&s"(save) : [v] "v"(lane * 16u), [r] "s"(r), [m] "s"(lds_base) : "memory");
+            } else if constexpr (V == 8) {
+                asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY16(0) RS_LDSCOPY16(1024) "s_mov_b32 m0, %[s]"
+                             : [s] "=&s"(save) : [v] "v"(lane * 16u), [r] "s"(r), [m] "s"(lds_base) : "memory");
+            } else {
+                static_assert(V == 16, "ensemble rounds");
+                asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY16(0) RS_LDSCOPY16(1024) RS_LDSCOPY16(2048)
+                             RS_LDSCOPY16(3072) "s_mov_b32 m0, %[s]"
+                             : [s] "=&s"(save) : [v] "v"(lane * 16u), [r] "s"(r), [m] "s"(lds_base) : "memory");
+            }
+            return;
+        }
+    }
     if constexpr (V == 1) {
         asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY(0) "s_mov_b32 m0, %[s]"
-                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+                     : [s] "=&s"(save) : [v] "v"(lane * 4u), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else if constexpr (V == 2) {
-        asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY(0) RS_LDSCOPY(256)
-                     "s_mov_b32 m0, %[s]"
-                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+        asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY(0) RS_LDSCOPY(256) "s_mov_b32 m0, %[s]"
+                     : [s] "=&s"(save) : [v] "v"(lane * 4u), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else if constexpr (V == 4) {
         asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY4(0, 256, 512, 768)
                      "s_mov_b32 m0, %[s]"
-                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+                     : [s] "=&s"(save) : [v] "v"(lane * 4u), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else if constexpr (V == 8) {
         asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY4(0, 256, 512, 768)
                      RS_LDSCOPY4(1024, 1280, 1536, 1792) "s_mov_b32 m0, %[s]"
-                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+                     : [s] "=&s"(save) : [v] "v"(lane * 4u), [r] "s"(r), [m] "s"(lds_base) : "memory");
     } else {
-        static_assert(V == 16, "ensemble rounds");
         asm volatile(RS_LDSCOPY_BEGIN RS_LDSCOPY4(0, 256, 512, 768)
                      RS_LDSCOPY4(1024, 1280, 1536, 1792) RS_LDSCOPY4(2048, 2304, 2560, 2816)
                      RS_LDSCOPY4(3072, 3328, 3584, 3840) "s_mov_b32 m0, %[s]"
-                     : [s] "=&s"(save) : [v] "v"(voff), [r] "s"(r), [m] "s"(lds_base) : "memory");
+                     : [s] "=&s"(save) : [v] "v"(lane * 4u), [r] "s"(r), [m] "s"(lds_base) : "memory");
     }
 }
 
@@ -690,7 +715,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 spos = 0xFFFFFFFFu;
                 if (pos < vend) {
                     lds_copy<V>(rsrc_words(elems + (size_t)pos * 4u, min(EW, vend - pos) * 4u), uni(lds_addr(fsl)),
-                                t * 4u);
+                                t, vend - pos >= EW);
                     spos = pos;
                 }
             }
@@ -1351,14 +1376,19 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             const uint32_t nr = (avail - base) >> 6;   // whole rounds short of a full ensemble
             if (nr) {
+                // every round's slot is read first (slots past the queue's end lie inside its
+                // array and are not used), so the reads overlap
+                uint32_t y[V > 1 ? V - 1 : 1];
+#pragma unroll
+                for (int k = 0; k + 1 < V; ++k) y[k] = q2v[base + (uint32_t)k * 64u + t];
 #pragma unroll
                 for (int k = 0; k + 1 < V; ++k) {
                     if ((uint32_t)k < nr) {
-                        const uint32_t y = fmix32(q2v[base + (uint32_t)k * 64u + t]);
-                        if (out_items) out_items[out_rank + (uint32_t)k * 64u + t] = y;
-                        acc.sum += (unsigned long long)y;
-                        acc.mn = min(acc.mn, y);
-                        acc.mx = max(acc.mx, y);
+                        const uint32_t v = fmix32(y[k]);
+                        if (out_items) out_items[out_rank + (uint32_t)k * 64u + t] = v;
+                        acc.sum += (unsigned long long)v;
+                        acc.mn = min(acc.mn, v);
+                        acc.mx = max(acc.mx, v);
                     }
                 }
                 acc.cnt += nr;
@@ -1456,11 +1486,11 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const bool ahead = nx < vend;
                 if (ahead)
                     lds_copy<V>(rsrc_words(elems + (size_t)nx * 4u, min(EW, vend - nx) * 4u),
-                                uni(in2 ? lds_addr(fsl) : lds_addr(q1v)), t * 4u);
+                                uni(in2 ? lds_addr(fsl) : lds_addr(q1v)), t, vend - nx >= EW);
                 const uint32_t npos = ahead ? nx : 0xFFFFFFFFu;
                 spos = in2 ? npos : spos;
                 spos2 = in2 ? spos2 : npos;
-                if (ahead) wait_vmem<V>(); else wait_vmem<0>();
+                if (ahead) wait_vmem<copy_ops<V>()>(); else wait_vmem<0>();
                 // ---- F and E, then A on every whole round
                 const uint32_t *src = in2 ? q1v : fsl;
                 const uint32_t nt = collect ? fuse_fe(BoolC<true>{}, src, lt) : fuse_fe(BoolC<false>{}, src, lt);
@@ -1769,7 +1799,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     if (q == (nnb >> 6)) ve = uni(__builtin_amdgcn_readlane(cur.off[q], nnb & 63u));
                 if (vb < ve && ve <= cur.n_elements) {
                     lds_copy<V>(rsrc_words(cur.elements + (size_t)vb * 4u, min(EW, ve - vb) * 4u), uni(lds_addr(fsl)),
-                                t * 4u);
+                                t, ve - vb >= EW);
                     pf_g = g;
                 }
             }

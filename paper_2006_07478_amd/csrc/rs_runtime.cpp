@@ -312,15 +312,16 @@ hipStream_t lane_of(rs_pipeline *p, uint64_t batch_id) {
 // parents, at least one parent.  Over u32 elements a claim takes about 32 ensembles when the
 // stream still makes enough such claims: at least 8192 (two for each of the about 4096 waves a
 // launch keeps resident) for aggregation, where each claim's fixed cost (its region table, its
-// records, its first copy) then falls on twice the elements; at least 2048 (8 per compute unit)
-// for an ordered output stream, whose claims start in index order and each wait on its
-// predecessor's output offset, so that fewer, larger claims shorten that chain.  Text lines,
-// whose lengths vary widely, and smaller streams keep 16.
+// records, its first copy) then falls on twice the elements, provided the claim keeps to 32
+// parents (more parents mean larger per-claim LDS arrays and fewer resident waves); at least
+// 2048 (8 per compute unit) for an ordered output stream, whose claims start in index order and
+// each wait on its predecessor's output offset, so that fewer, larger claims shorten that chain.
+// Text lines, whose lengths vary widely, and smaller streams keep 16.
 void claim_plan(uint32_t kind, bool ordered_out, uint32_t width, uint32_t n_parents, double mean_len, uint32_t *B,
                 uint32_t *n_claims) {
     const double bmax = rs::claim_parents_max(width);
     const double min_claims = ordered_out ? 2048.0 : 8192.0;
-    const bool big = kind != RS_TEXT_WORDS && mean_len > 0 &&
+    const bool big = kind != RS_TEXT_WORDS && mean_len > 0 && (ordered_out || 32.0 * width / mean_len <= 32.0) &&
                      (double)n_parents * mean_len >= min_claims * 32.0 * width;
     const double b = mean_len > 0 ? (big ? 32.0 : 16.0) * width / mean_len : bmax;
     *B = (uint32_t)std::max(1.0, std::min(bmax, b));
