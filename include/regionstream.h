@@ -104,9 +104,14 @@ typedef struct rs_pipeline rs_pipeline;   /* opaque, library-owned */
  *   ensemble_width  0 = autotune, else 64, 128, 256, 512 or 1024: the SIMD width w, the largest
  *                   ensemble one firing of a node consumes (§2.2; one wave64 processes w/64
  *                   items per lane per firing)
- *   queue_depth     0 = default; else the capacity in slots of the queue in front of every
- *                   stage, a power of two >= 2*ensemble_width (the stage maxima need room for
- *                   k*w outputs plus signal slots, §3.2 fireability)
+ *   queue_depth     0 = tuned with strategy and width when either is left to the autotuner
+ *                   (2w or 4w), else 2w; otherwise a power of two in [2w, 8w]: the slots of the
+ *                   queue in front of the second stage; the queue in front of the aggregating
+ *                   stage holds as many, and one ensemble more behind the expansion (whose k = 3
+ *                   worst case must fit above a leftover).  A node fires only when its downstream
+ *                   queue has room for what the firing may produce (§3.2 fireability), so the
+ *                   depth decides when nodes fire, never what they compute.  Refused when the
+ *                   queues do not fit a compute unit's LDS at the width.
  *   emit_outputs    1 = also produce the ordered surviving-item stream (read_outputs)
  *   flags           RS_COLLECT_STATS | RS_NO_GRAPH | RS_TIME_KERNEL
  *   hbm_budget_bytes  0 = unlimited; else streams are admitted to a run only while the device
@@ -269,8 +274,8 @@ int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view *out, 
  * in one persistent launch, with no allocation of any kind.  The library's device state for the
  * call (control block, stream table, statistics: about 12 KB) lives in one static array per device,
  * held until the process ends; the caller passes inputs and outputs.
- *   d          as for pipeline_create, with an explicit strategy (not RS_AUTO) and ensemble width,
- *              emit_outputs = 0 and queue_depth 0 or 2 * ensemble_width
+ *   d          as for pipeline_create, with an explicit strategy (not RS_AUTO) and ensemble width
+ *              and emit_outputs = 0 (queue_depth 0 means 2w)
  *   streams    n_streams stream descriptions, mem = RS_MEM_DEVICE (borrowed until the launch ends)
  *   out        n_streams destinations: device arrays [n_parents] of every field in agg_fields
  *   hip_stream HIP stream the launch is enqueued on (NULL: the default stream)

@@ -60,7 +60,7 @@ struct LaunchArgs {
     uint32_t bmax;                 // most parents in any claim of the launch (sizes the per-claim LDS)
     uint32_t n_parts;              // claim partitions: CTL_NPART, or 1 when claims must start in order
     uint32_t lb_wait_us;           // longest wait of one look-back step on a predecessor claim (microseconds)
-    uint32_t pad;
+    uint32_t qdepth;               // queue depth: a power of two in [2w, 8w] (data slots of the first queue)
 };
 
 // The no-allocation entry point (run_noalloc) keeps its device state in one static array of
@@ -86,9 +86,10 @@ bool kernel_supported(uint32_t kind, uint32_t strategy, uint32_t width);
 // (HIP events) are recorded directly before and after the pipeline kernel.
 int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const LaunchArgs &a,
                     uint32_t grid, void *stream, void *ev_begin = nullptr, void *ev_end = nullptr);
-int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t bmax);
-// Bytes of per-claim LDS (region table and aggregate slots) for claims of up to bmax parents.
-uint32_t dyn_lds_bytes(uint32_t kind, uint32_t bmax);
+int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t qdepth, uint32_t bmax);
+// Bytes of dynamic LDS: the data queues for queue depth qdepth, and the per-claim arrays (region
+// table and aggregate slots) for claims of up to bmax parents.
+uint32_t dyn_lds_bytes(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t qdepth, uint32_t bmax);
 int launch_probe_copy(const void *src, void *dst, unsigned long long bytes, uint32_t n_cu, void *stream);
 // Device address of the no-allocation scratch array on the current device (looked up once per
 // device with hipGetSymbolAddress; the array itself is file-scope in rs_kernels.hip).

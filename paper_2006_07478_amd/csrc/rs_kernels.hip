@@ -178,16 +178,11 @@ __device__ __forceinline__ void lds_copy(u32x4 r, uint32_t lds_base, uint32_t la
     }
 }
 
-// Slot of queue position base + i in a ring of D slots, where base < D and i < D: a mask for
-// a power of two, else one conditional subtraction written as an unsigned minimum.
-template <uint32_t D>
-__device__ __forceinline__ uint32_t qslot(uint32_t base, uint32_t i) {
-    if constexpr ((D & (D - 1u)) == 0u) {
-        return (base + i) & (D - 1u);
-    } else {
-        const uint32_t p = base + i;
-        return min(p, p - D);
-    }
+// Slot of queue position base + i in a ring of d slots, where base < d and i < d: one
+// conditional subtraction, written as an unsigned minimum.
+__device__ __forceinline__ uint32_t qslot(uint32_t d, uint32_t base, uint32_t i) {
+    const uint32_t p = base + i;
+    return min(p, p - d);
 }
 
 // a where the lane's bit of mask is set, else b (one v_cndmask, never a branch).  The mask is
@@ -340,27 +335,43 @@ __device__ __forceinline__ uint32_t bits_below(const uint64_t (&m)[V], uint32_t 
 
 // ---------------------------------------------------------------- geometry
 
-template <int V, bool HAS_E, uint32_t KE>
+template <int V>
 struct Geo {
     static constexpr uint32_t EW = 64u * V;   // ensemble width: items one firing consumes
-    static constexpr uint32_t D1 = 2u * EW;   // data slots in front of the second node
-    // in front of the third node: the third node drains it below one ensemble before the
-    // second fires, so room for one full ensemble's worst-case output (KE per input) on top
-    // lets the second node always fire full ensembles
-    static constexpr uint32_t D2 = HAS_E ? (KE == 3u ? 3u * EW : 2u * EW) : 1u;
     static constexpr uint32_t SQ = 64u;       // signal queue capacity (the finite S of §3.1)
     static constexpr uint32_t R = 4u;         // region-table rows per lane (256 entries)
 };
 
-// Per-claim LDS arrays, sized at launch for the batch's largest claim (bmax parents).
+// Data-queue depths for queue depth q (the pipeline's queue_depth: a power of two, at least 2w):
+// the queue in front of the second node holds q items; the one in front of the third node holds
+// q, and one ensemble more behind the expansion (its consumer drains it below one ensemble
+// before the expansion fires, so room for one full ensemble's worst case of 3w on top lets the
+// expansion always fire full ensembles; at q = 2w that is the 3w of that argument).
+__host__ __device__ inline uint32_t depth2(uint32_t kind, uint32_t ew, uint32_t q) {
+    return kind == RS_HASH_EXPAND ? q + ew : kind == RS_TEXT_WORDS ? q : 1u;
+}
+
+// LDS arrays sized at launch: the data queues (for the queue depth q), each followed by 64
+// spill slots (one per lane) for dropped items, and the per-claim arrays for the batch's largest
+// claim (bmax parents).  Fused firings (hash kind) use the third node's queue as a plain array of
+// 3w + 66 slots (a leftover of under 64 items, up to 3w children and two slots a firing may write
+// past its last child) followed by 66 dump slots.
 struct Dyn {
-    uint32_t sum, vt, sx, cx, cnt, mn, mx, bytes;
+    uint32_t q1v, q2v, q1a, q1t, q2t, sum, vt, sx, cx, cnt, mn, mx, bytes;
 };
-__host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t bmax) {
+__host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t strategy, uint32_t ew, uint32_t q, uint32_t bmax) {
+    const bool tag = strategy == RS_TAG, has_e = kind == RS_HASH_EXPAND || kind == RS_TEXT_WORDS;
+    const uint32_t d2 = depth2(kind, ew, q);
+    uint32_t q2 = has_e ? d2 + 64u : 0u;
+    if (kind == RS_HASH_EXPAND && q2 < 3u * ew + 132u) q2 = 3u * ew + 132u;
     Dyn d;
     uint32_t o = 0;
     d.sum = o;
     o += 8u * bmax;   // u64 slots first (8-byte aligned)
+    d.q1v = o;
+    o += 4u * (q + 64u);
+    d.q2v = o;
+    o += 4u * q2;
     d.vt = o;
     o += 4u * (bmax + 1u);
     d.sx = o;
@@ -373,6 +384,12 @@ __host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t bmax) {
     o += 4u * bmax;
     d.mx = o;
     o += 4u * bmax;
+    d.q1a = o;
+    if (kind == RS_HASH_EXPAND) o += q + 64u;
+    d.q1t = o;
+    if (tag) o += q + 64u;
+    d.q2t = o;
+    if (tag && has_e) o += d2 + 64u;
     d.bytes = (o + 15u) & ~15u;
     return d;
 }
@@ -435,26 +452,24 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     constexpr bool BYTES = (KIND == RS_TEXT_WORDS);
     constexpr bool CTXP = (KIND == RS_GRAPH_THRESH);
     constexpr uint32_t KE = (KIND == RS_HASH_EXPAND) ? 3u : 1u;   // outputs per input of E, at most
-    using G = Geo<V, HAS_E, KE>;
-    constexpr uint32_t EW = G::EW, D1 = G::D1, D2 = G::D2, SQ = G::SQ, R = G::R;
-    constexpr uint32_t DA = HAS_E ? D2 : D1;   // the aggregating node's input queue
+    using G = Geo<V>;
+    constexpr uint32_t EW = G::EW, SQ = G::SQ, R = G::R;
+    const uint32_t D1 = a.qdepth;                       // data slots in front of the second node
+    const uint32_t D2 = depth2(KIND, EW, D1);           // in front of the third node
+    const uint32_t DA = HAS_E ? D2 : D1;                // the aggregating node's input queue
     static_assert(!LANES || (KIND != RS_TEXT_WORDS && V <= 4), "lane-resolved signals: u32 kinds, w <= 256");
-
-    // data queues, each followed by 64 spill slots (one per lane) for dropped items
-    __shared__ uint32_t q1v[D1 + 64];
-    __shared__ uint8_t q1a[KIND == RS_HASH_EXPAND ? D1 + 64 : 1];
-    __shared__ uint8_t q1t[TAG ? D1 + 64 : 1];
-    // fused firings (hash kind, below) use A's queue as a plain array: a leftover of under 64
-    // items, up to 3w children and two slots that a firing may write past its last child, then
-    // one dump slot (plus two) per lane for lanes without children
-    constexpr bool FUSE = (KIND == RS_HASH_EXPAND);
+    constexpr bool FUSE = (KIND == RS_HASH_EXPAND);   // fused firings, below
     constexpr uint32_t FL = 3u * EW + 66u, FDUMP = FL;
-    __shared__ uint32_t q2v[HAS_E ? (FUSE ? (D2 + 64u > FL + 66u ? D2 + 64u : FL + 66u) : D2 + 64u) : 1];
-    __shared__ uint8_t q2t[(HAS_E && TAG) ? D2 + 64 : 1];
+
     __shared__ uint32_t fsl[BYTES ? 1 : EW];   // staging slot for the enumerating node's next ensemble
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
 
-    const Dyn lay = dyn_layout(KIND, a.bmax);
+    const Dyn lay = dyn_layout(KIND, STRAT, EW, D1, a.bmax);
+    uint32_t *const q1v = (uint32_t *)(dyn + lay.q1v);
+    uint8_t *const q1a = dyn + lay.q1a;                 // the expansion's child count per item
+    uint8_t *const q1t = dyn + lay.q1t;                 // tags
+    uint32_t *const q2v = (uint32_t *)(dyn + lay.q2v);
+    uint8_t *const q2t = dyn + lay.q2t;
     unsigned long long *const s_sum = (unsigned long long *)(dyn + lay.sum);
     uint32_t *const VT = (uint32_t *)(dyn + lay.vt);    // region starts in enumeration order, end at [nb]
     uint32_t *const SX = (uint32_t *)(dyn + lay.sx);    // region start addresses (start+length streams)
@@ -973,7 +988,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             uint32_t y[V], tg[V];
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                const uint32_t pos = qslot<DA>(hw, (uint32_t)k * 64u + t);
+                const uint32_t pos = qslot(DA, hw, (uint32_t)k * 64u + t);
                 y[k] = qv[pos];
                 if constexpr (TAG) tg[k] = qt[pos]; else tg[k] = 0u;
             }
@@ -1100,7 +1115,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             if constexpr (HAS_E) {
                 h2 += e;
-                h2w = qslot<D2>(h2w, e);
+                h2w = qslot(D2, h2w, e);
             } else {
                 h1 += e;
             }
@@ -1180,7 +1195,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     uint32_t within = rank_below(b0[k]);
                     if constexpr (KE == 3u) within += 2u * rank_below(b1[k]);
                     const uint32_t off = run + within;
-                    const uint32_t slot0 = qslot<D2>(t2w, off);   // first child's slot
+                    const uint32_t slot0 = qslot(D2, t2w, off);   // first child's slot
                     uint64_t fits = 0;
                     if constexpr (!FIT) {
                         fits = __ballot(act && off + nout <= room);
@@ -1189,7 +1204,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     }
 #pragma unroll
                     for (uint32_t ch = 0; ch < KE; ++ch) {
-                        const uint32_t sl = ch == 0u ? slot0 : qslot<D2>(slot0, ch);
+                        const uint32_t sl = ch == 0u ? slot0 : qslot(D2, slot0, ch);
                         const uint64_t m = FIT ? __ballot(ch < nout) : (__ballot(ch < nout) & fits);
                         const uint32_t pos = pick(m, sl, D2 + t);
                         // child ch of x leaves as its pre-image x ^ K(ch+1) (hash kind); a word as its length
@@ -1226,7 +1241,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             h1 += taken;
             t2 += made;
-            t2w = qslot<D2>(t2w, made);
+            t2w = qslot(D2, t2w, made);
             stat(ST_FIRINGS + 1, 1u);
             stat(ST_ITEMS + 1, taken);
             stat(ST_FULL + 1, taken == EW ? 1u : 0u);
@@ -1861,7 +1876,9 @@ static KernelFn pick(uint32_t kind, uint32_t s, uint32_t w) {
 
 uint32_t lanes_of(uint32_t ensemble_width) { return ensemble_width ? 64u : 0u; }
 
-uint32_t dyn_lds_bytes(uint32_t kind, uint32_t bmax) { return dyn_layout(kind, bmax).bytes; }
+uint32_t dyn_lds_bytes(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t qdepth, uint32_t bmax) {
+    return dyn_layout(kind, strategy, width, qdepth, bmax).bytes;
+}
 
 // ---------------------------------------------------------------- HBM probe
 
@@ -1948,17 +1965,19 @@ int launch_pipeline(uint32_t kind, uint32_t strategy, uint32_t width, const Laun
     hipLaunchKernelGGL(rs_reset, dim3(1), dim3(64), 0, st, a.ctl);
     hipError_t e = hipSuccess;
     if (ev_begin && (e = hipEventRecord((hipEvent_t)ev_begin, st)) != hipSuccess) return (int)e;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), dyn_lds_bytes(kind, a.bmax), st, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(lanes_of(width)), dyn_lds_bytes(kind, strategy, width, a.qdepth, a.bmax), st,
+                       a);
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
     if (ev_end && (e = hipEventRecord((hipEvent_t)ev_end, st)) != hipSuccess) return (int)e;
     return (int)hipSuccess;
 }
 
-int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t bmax) {
+int blocks_per_cu(uint32_t kind, uint32_t strategy, uint32_t width, uint32_t qdepth, uint32_t bmax) {
     KernelFn k = pick(kind, strategy, width);
     if (!k) return 0;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)lanes_of(width), dyn_lds_bytes(kind, bmax)) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)lanes_of(width),
+                                                    dyn_lds_bytes(kind, strategy, width, qdepth, bmax)) !=
         hipSuccess)
         return 0;
     return n;

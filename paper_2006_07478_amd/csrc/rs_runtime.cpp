@@ -189,7 +189,7 @@ struct Batch {
     DevBuf table, ctl;
     uint32_t total_claims = 0;
     uint32_t grid = 0;
-    uint32_t strategy = 0, width = 0;
+    uint32_t strategy = 0, width = 0, qdepth = 0;
     rs::LaunchArgs args{};
     hipStream_t lane = nullptr;
     uint64_t launches = 0;         // launches of this batch (its control block counts them too)
@@ -214,7 +214,7 @@ struct rs_pipeline {
     hipStream_t copy = nullptr;    // host-to-device copies of pushed streams, apart from the launch lanes
     hipStream_t user_stream = nullptr;
     bool one_lane = false;         // every batch on the first lane (the per-stream baseline)
-    uint32_t width = 0, strategy = 0;
+    uint32_t width = 0, strategy = 0, qdepth = 0;
     bool configured = false;
     uint64_t next_id = 1, next_batch = 1;
     uint64_t admitted_bytes = 0;
@@ -234,21 +234,24 @@ std::string cache_path() {
     const char *xdg = getenv("XDG_CACHE_HOME");
     const char *home = getenv("HOME");
     std::string dir = xdg ? std::string(xdg) : home ? std::string(home) + "/.cache" : std::string("/tmp");
-    return dir + "/regionstream-autotune-gfx950.txt";
+    return dir + "/regionstream-autotune-gfx950-v2.txt";
 }
 
 int length_bucket(double mean_len) { return (int)std::lround(2.0 * std::log2(std::max(mean_len, 0.5))); }
 
-bool cache_lookup(uint32_t kind, uint32_t emit, int bucket, uint32_t *strategy, uint32_t *width) {
+bool depth_ok(uint32_t width, uint32_t q) { return q && !(q & (q - 1)) && q >= 2 * width && q <= 8 * width; }
+
+bool cache_lookup(uint32_t kind, uint32_t emit, int bucket, uint32_t *strategy, uint32_t *width, uint32_t *depth) {
     FILE *f = fopen(cache_path().c_str(), "r");
     if (!f) return false;
-    unsigned k, e, s, w;
+    unsigned k, e, s, w, q;
     int b;
     bool found = false;
-    while (fscanf(f, "%u %u %d %u %u", &k, &e, &b, &s, &w) == 5) {
-        if (k == kind && e == emit && b == bucket && s != RS_AUTO && rs::kernel_supported(k, s, w)) {
+    while (fscanf(f, "%u %u %d %u %u %u", &k, &e, &b, &s, &w, &q) == 6) {
+        if (k == kind && e == emit && b == bucket && s != RS_AUTO && rs::kernel_supported(k, s, w) && depth_ok(w, q)) {
             *strategy = s;
             *width = w;
+            *depth = q;
             found = true;   // the last line for a key wins
         }
     }
@@ -256,10 +259,10 @@ bool cache_lookup(uint32_t kind, uint32_t emit, int bucket, uint32_t *strategy, 
     return found;
 }
 
-void cache_store(uint32_t kind, uint32_t emit, int bucket, uint32_t strategy, uint32_t width) {
+void cache_store(uint32_t kind, uint32_t emit, int bucket, uint32_t strategy, uint32_t width, uint32_t depth) {
     FILE *f = fopen(cache_path().c_str(), "a");
     if (!f) return;
-    fprintf(f, "%u %u %d %u %u\n", kind, emit, bucket, strategy, width);
+    fprintf(f, "%u %u %d %u %u %u\n", kind, emit, bucket, strategy, width, depth);
     fclose(f);
 }
 
@@ -350,6 +353,7 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     std::unique_ptr<Batch> b(new Batch);
     b->strategy = p->strategy;
     b->width = p->width;
+    b->qdepth = p->qdepth;
     b->lane = lane_of(p, batch_id);
     std::vector<rs::StreamDev> h(sel.size());
     uint64_t claims = 0;
@@ -402,7 +406,7 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     HIP_OR(hipStreamSynchronize(b->lane), RS_EDEVICE);   // h is a local array
     HIP_OR(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), RS_EDEVICE);
     b->total_claims = (uint32_t)claims;
-    const int per_cu = rs::blocks_per_cu(p->d.kind, p->strategy, p->width, bmax);
+    const int per_cu = rs::blocks_per_cu(p->d.kind, p->strategy, p->width, p->qdepth, bmax);
     if (per_cu <= 0) return fail(RS_EDEVICE, "kernel does not fit on a compute unit");
     // every workgroup holds two claims at a time (the next one's region table is prefetched)
     b->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((claims + 1) / 2, (uint64_t)per_cu * p->n_cu));
@@ -419,6 +423,7 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     // the ordered output stream's look-back needs claims taken in index order, from one counter
     a.n_parts = a.emit_outputs ? 1u : rs::CTL_NPART;
     a.lb_wait_us = lookback_wait_us();
+    a.qdepth = p->qdepth;
     out = std::move(b);
     return RS_OK;
 }
@@ -516,16 +521,18 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
         parents += s->n_parents;
     }
     const int bucket = length_bucket(parents > 0 ? covered / parents : 0.0) + (sel.size() > 1 ? 1000 : 0);
-    const uint32_t want_s = p->d.strategy, want_w = p->d.ensemble_width;
-    uint32_t cs = 0, cw = 0;
-    if (cache_lookup(p->d.kind, p->d.emit_outputs, bucket, &cs, &cw) && (want_s == RS_AUTO || want_s == cs) &&
-        (want_w == 0 || want_w == cw)) {
+    const uint32_t want_s = p->d.strategy, want_w = p->d.ensemble_width, want_q = p->d.queue_depth;
+    uint32_t cs = 0, cw = 0, cq = 0;
+    if (cache_lookup(p->d.kind, p->d.emit_outputs, bucket, &cs, &cw, &cq) && (want_s == RS_AUTO || want_s == cs) &&
+        (want_w == 0 || want_w == cw) && (want_q == 0 || want_q == cq)) {
         p->strategy = cs;
         p->width = cw;
+        p->qdepth = cq;
         return RS_OK;
     }
     float best = 1e30f;
     uint32_t best_s = want_s == RS_AUTO ? RS_TAG : want_s, best_w = want_w ? want_w : 256;
+    uint32_t best_q = want_q ? want_q : 2 * best_w;
     hipEvent_t e0, e1;
     HIP_OR(hipEventCreate(&e0), RS_EDEVICE);
     HIP_OR(hipEventCreate(&e1), RS_EDEVICE);
@@ -533,11 +540,18 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
     for (uint32_t strat : {(uint32_t)RS_TAG, (uint32_t)RS_SIGNAL, (uint32_t)RS_SIGNAL_LANES}) {
         if (rc != RS_OK) break;
         if (want_s != RS_AUTO && strat != want_s) continue;
-        for (uint32_t w : kWidths) {
+        for (uint32_t wq = 0; wq < 2 * (sizeof kWidths / sizeof kWidths[0]) && rc == RS_OK; ++wq) {
+            // every width at queue depths 2w and 4w (or at the depth asked for)
+            const uint32_t w = kWidths[wq / 2];
             if (want_w && w != want_w) continue;
             if (!rs::kernel_supported(p->d.kind, strat, w)) continue;
+            if (want_q && (wq % 2 || !depth_ok(w, want_q))) continue;
+            const uint32_t q = want_q ? want_q : (wq % 2 ? 4 * w : 2 * w);
+            // the queues and a full claim's arrays must fit a compute unit's LDS
+            if (rs::blocks_per_cu(p->d.kind, strat, w, q, rs::claim_parents_max(w)) <= 0) continue;
             p->strategy = strat;
             p->width = w;
+            p->qdepth = q;
             std::unique_ptr<Batch> b;
             if ((rc = make_batch(p, probe, 0, true, b))) break;
             if ((rc = launch_batch(p, *b, false))) break;   // warm-up
@@ -555,6 +569,7 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
                 best = ms;
                 best_s = strat;
                 best_w = w;
+                best_q = q;
             }
         }
     }
@@ -563,7 +578,8 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
     if (rc) return rc;
     p->strategy = best_s;
     p->width = best_w;
-    cache_store(p->d.kind, p->d.emit_outputs, bucket, best_s, best_w);
+    p->qdepth = best_q;
+    cache_store(p->d.kind, p->d.emit_outputs, bucket, best_s, best_w, best_q);
     return RS_OK;
 }
 
@@ -632,7 +648,13 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     if (d->queue_depth) {
         const uint32_t q = d->queue_depth;
         if (q & (q - 1)) return fail(RS_EINVAL, "queue_depth must be a power of two");
-        if (w && q != 2 * w) return fail(RS_EINVAL, "queue_depth %u: this build sizes queues at 2 * ensemble_width", q);
+        if (w && !depth_ok(w, q))
+            return fail(RS_EINVAL, "queue_depth %u must lie in [2w, 8w] = [%u, %u]", q, 2 * w, 8 * w);
+        if (!w && (q < 128 || q > 8192))
+            return fail(RS_EINVAL, "queue_depth %u fits no ensemble width (2w <= depth <= 8w)", q);
+        if (w && d->strategy != RS_AUTO &&
+            rs::blocks_per_cu(d->kind, d->strategy, w, q, rs::claim_parents_max(w)) <= 0)
+            return fail(RS_EINVAL, "queue_depth %u: the queues do not fit a compute unit's LDS at this width", q);
     }
     if (d->emit_outputs > 1) return fail(RS_EINVAL, "emit_outputs must be 0 or 1");
     if (d->flags & ~7u) return fail(RS_EINVAL, "unknown pipeline flags");
@@ -653,6 +675,8 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     }
     p->width = d->ensemble_width;
     p->strategy = d->strategy == RS_AUTO ? RS_TAG : d->strategy;
+    // queue_depth 0: twice the width when strategy and width are given, else tuned with them
+    p->qdepth = d->queue_depth ? d->queue_depth : 2 * d->ensemble_width;
     p->configured = d->ensemble_width != 0 && d->strategy != RS_AUTO;
     *out = p.release();
     return RS_OK;
@@ -936,7 +960,7 @@ RS_API int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out) {
     auto bi = p->batches.find(s->batch);
     if (bi != p->batches.end()) {
         out->ensemble_width = bi->second->width;
-        out->queue_depth = 2 * bi->second->width;
+        out->queue_depth = bi->second->qdepth;
         out->strategy = bi->second->strategy;
         out->n_workgroups = bi->second->grid;
     }
@@ -1100,8 +1124,9 @@ RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams,
     if (d->agg_fields == 0 || (d->agg_fields & ~15u))
         return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX");
     if (d->emit_outputs) return fail(RS_EINVAL, "run_noalloc does not produce the ordered output stream");
-    if (d->queue_depth && d->queue_depth != 2 * d->ensemble_width)
-        return fail(RS_EINVAL, "queue_depth %u: this build sizes queues at 2 * ensemble_width", d->queue_depth);
+    const uint32_t qdepth = d->queue_depth ? d->queue_depth : 2 * d->ensemble_width;
+    if (!depth_ok(d->ensemble_width, qdepth))
+        return fail(RS_EINVAL, "queue_depth %u must be a power of two in [2w, 8w]", qdepth);
     if (d->kind == RS_MODFILTER && d->param[0] != 0 && d->param[1] >= d->param[0])
         return fail(RS_EINVAL, "residue must be smaller than the modulus");
     const bool text = d->kind == RS_TEXT_WORDS;
@@ -1158,8 +1183,8 @@ RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams,
     int dev = 0, n_cu = 0;
     HIP_OR(hipGetDevice(&dev), RS_EDEVICE);
     HIP_OR(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), RS_EDEVICE);
-    const int per_cu = rs::blocks_per_cu(d->kind, d->strategy, d->ensemble_width, bmax);
-    if (per_cu <= 0) return fail(RS_EDEVICE, "kernel does not fit on a compute unit");
+    const int per_cu = rs::blocks_per_cu(d->kind, d->strategy, d->ensemble_width, qdepth, bmax);
+    if (per_cu <= 0) return fail(RS_EINVAL, "the queues do not fit a compute unit's LDS at this width and depth");
     rs::LaunchArgs a{};
     a.streams = (const rs::StreamDev *)((uint8_t *)base + rs::NOALLOC_TABLE_OFF);
     a.ctl = (uint32_t *)((uint8_t *)base + rs::NOALLOC_CTL_OFF);
@@ -1172,6 +1197,7 @@ RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams,
     a.bmax = bmax;
     a.n_parts = rs::CTL_NPART;
     a.lb_wait_us = lookback_wait_us();
+    a.qdepth = qdepth;
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((claims + 1) / 2, (uint64_t)per_cu * n_cu));
     hrc = rs::launch_noalloc_init(base, tab, hip_stream);
     if (hrc) return fail(RS_EDEVICE, "init launch: %s", hipGetErrorString((hipError_t)hrc));

@@ -56,10 +56,10 @@ def check(got, ref, fields=("count", "sum", "min", "max"), where=""):
 
 
 def run_one(kind, strategy, width, offsets, elements, lengths=None, parent_param=None, param=(0, 0, 0, 0),
-            fields=ALL, device=False, flags=0):
+            fields=ALL, device=False, flags=0, queue_depth=0):
     import torch
     with rs.Pipeline(kind, strategy=strategy, ensemble_width=width, agg_fields=fields, param=param,
-                     flags=flags) as p:
+                     flags=flags, queue_depth=queue_depth) as p:
         if device:
             to = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a).view(
                 np.int32 if a.dtype == np.uint32 else np.uint8)).cuda()
@@ -468,6 +468,7 @@ def test_autotuned_pipeline_matches_oracle(tmp_path, monkeypatch):
                 st = p.stats(sid)
                 assert st.ensemble_width in WIDTHS
                 assert st.strategy in strats(rs.RS_HASH_EXPAND, st.ensemble_width)
+                assert st.queue_depth in (2 * st.ensemble_width, 4 * st.ensemble_width)
     lines = (tmp_path / "tune.txt").read_text().split("\n")
     assert len([l for l in lines if l.strip()]) == 2
 
@@ -517,6 +518,29 @@ def test_every_autotune_candidate(kind, strategy, width):
                      parent_param=inp.get("parent_param"), param=inp.get("param", (0, 0, 0, 0)), fields=fields,
                      device=True)
     check(got, ref, [n for n, bit, _ in rs.FIELDS if fields & bit], f"candidate {kind} {SNAME[strategy]} w={width}")
+
+
+@pytest.mark.parametrize("factor", [4, 8])
+@pytest.mark.parametrize("width", [64, 256])
+@pytest.mark.parametrize("strategy", ALL3)
+@pytest.mark.parametrize("kind", [rs.RS_MODFILTER, rs.RS_HASH_EXPAND, rs.RS_TEXT_WORDS, rs.RS_GRAPH_THRESH])
+def test_queue_depths(kind, strategy, width, factor):
+    """Queue depths 4w and 8w (every other test runs the default 2w; the autotuner picks 2w or 4w)
+    against the oracle: a node fires against the space left in its downstream queue (§3.2), so the
+    depth changes when nodes fire, never what they compute."""
+    skip_unoffered(kind, strategy, width)
+    if kind not in _CAND:
+        _CAND.clear()
+        _CAND[kind] = candidate_inputs(kind)
+    inp, ref = _CAND[kind]
+    say("queue depth", kind, SNAME[strategy], width, factor * width)
+    fields = rs.DEFAULT_FIELDS[kind]
+    got, st = run_one(kind, strategy, width, inp["offsets"], inp["elements"], lengths=inp.get("lengths"),
+                      parent_param=inp.get("parent_param"), param=inp.get("param", (0, 0, 0, 0)), fields=fields,
+                      device=True, queue_depth=factor * width, flags=rs.RS_COLLECT_STATS)
+    assert st.queue_depth == factor * width
+    check(got, ref, [n for n, bit, _ in rs.FIELDS if fields & bit],
+          f"queue depth {factor}w {kind} {SNAME[strategy]} w={width}")
 
 
 def test_lookback_give_up_reports_a_device_error(monkeypatch):
