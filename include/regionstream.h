@@ -55,8 +55,14 @@ enum rs_status {
  * RS_SIGNAL_LANES: the lane-resolved signals the paper proposes as future work (§6): the same
  * signal queues, but an ensemble may span boundaries and every node computes each lane's
  * region from the pending signals' positions instead of storing it with the items.  Offered for
- * u32 kinds (not RS_TEXT_WORDS) at ensemble widths 64, 128 and 256. */
-enum rs_strategy { RS_TAG = 0, RS_SIGNAL = 1, RS_AUTO = 2, RS_SIGNAL_LANES = 3 };
+ * u32 kinds (not RS_TEXT_WORDS) at ensemble widths 64, 128 and 256.
+ * RS_ENUM_TAG: a choice per stage, the second version of the paper's taxi application (§5): the
+ * enumerating stage works one region at a time, as under signals, and tags every item it emits
+ * with that region, so the later stages work as under tags, their ensembles spanning regions.
+ * Offered for the kinds with a second stage (RS_HASH_EXPAND, RS_TEXT_WORDS).  The autotuner
+ * therefore chooses per stage among signals on both edges (RS_SIGNAL), enumeration then tags
+ * (RS_ENUM_TAG) and tags on both (RS_TAG), besides lane-resolved signals. */
+enum rs_strategy { RS_TAG = 0, RS_SIGNAL = 1, RS_AUTO = 2, RS_SIGNAL_LANES = 3, RS_ENUM_TAG = 4 };
 
 /* Stage kinds (hand-written HIP stages; there is no user device code).
  *   RS_MODFILTER    u32 elements; keep x mod param[0] == param[1] (param[0] 0 means 4); k = 1.

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libregionstream.so")
 
 ABI_VERSION = 1
 RS_OK, RS_EINVAL, RS_ENOMEM, RS_EDEVICE, RS_EBUDGET, RS_ENOTREADY, RS_ESTATE, RS_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
-RS_TAG, RS_SIGNAL, RS_AUTO, RS_SIGNAL_LANES = 0, 1, 2, 3
+RS_TAG, RS_SIGNAL, RS_AUTO, RS_SIGNAL_LANES, RS_ENUM_TAG = 0, 1, 2, 3, 4
 RS_MODFILTER, RS_HASH_EXPAND, RS_TEXT_WORDS, RS_GRAPH_THRESH = 1, 2, 3, 4
 RS_COUNT, RS_SUM, RS_MIN, RS_MAX = 1, 2, 4, 8
 RS_MEM_HOST, RS_MEM_DEVICE = 0, 1

@@ -360,7 +360,8 @@ struct Dyn {
     uint32_t q1v, q2v, q1a, q1t, q2t, sum, vt, sx, cx, cnt, mn, mx, bytes;
 };
 __host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t strategy, uint32_t ew, uint32_t q, uint32_t bmax) {
-    const bool tag = strategy == RS_TAG, has_e = kind == RS_HASH_EXPAND || kind == RS_TEXT_WORDS;
+    const bool tag = strategy == RS_TAG || strategy == RS_ENUM_TAG;   // items carry tags
+    const bool has_e = kind == RS_HASH_EXPAND || kind == RS_TEXT_WORDS;
     const uint32_t d2 = depth2(kind, ew, q);
     uint32_t q2 = has_e ? d2 + 64u : 0u;
     if (kind == RS_HASH_EXPAND && q2 < 3u * ew + 132u) q2 = 3u * ew + 132u;
@@ -445,9 +446,16 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     // lane-resolved signals: ensembles span region boundaries, the boundaries travel on the
     // signal queues only, and every node computes each lane's region from the pending signals
     constexpr bool LANES = (STRAT == RS_SIGNAL_LANES);
-    // the enumerating node walks consecutive positions and the aggregating node resolves regions
-    // per lane (tags, or lane-resolved signals); plain signals cap every ensemble at its region
+    // per-stage choice (the second taxi version of §5): the enumerating node walks one region at a
+    // time, as under signals, and tags each item it emits with that region; downstream nodes work
+    // as under tags, their ensembles spanning regions
+    constexpr bool HYB = (STRAT == RS_ENUM_TAG);
+    // the enumerating node walks consecutive positions (tags, lane-resolved signals); under
+    // signals and the per-stage choice it walks one region at a time
     constexpr bool WALK = TAG || LANES;
+    constexpr bool TAGQ = TAG || HYB;                    // queued items carry their region's tag
+    constexpr bool SIGQ = (STRAT == RS_SIGNAL);          // signals cap every downstream ensemble
+    constexpr bool PERLANE = WALK || HYB;                // the aggregating node resolves regions per lane
     constexpr bool HAS_E = (KIND == RS_HASH_EXPAND || KIND == RS_TEXT_WORDS);
     constexpr bool BYTES = (KIND == RS_TEXT_WORDS);
     constexpr bool CTXP = (KIND == RS_GRAPH_THRESH);
@@ -990,7 +998,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             for (int k = 0; k < V; ++k) {
                 const uint32_t pos = qslot(DA, hw, (uint32_t)k * 64u + t);
                 y[k] = qv[pos];
-                if constexpr (TAG) tg[k] = qt[pos]; else tg[k] = 0u;
+                if constexpr (TAGQ) tg[k] = qt[pos]; else tg[k] = 0u;
             }
             if constexpr (LANES) {
                 // each lane's region: the head region ja plus the pending signals at or before its
@@ -1008,7 +1016,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
             }
             uint32_t tf = 0, tl = 0;
-            if constexpr (WALK) {
+            if constexpr (PERLANE) {
                 // regions of the ensemble's first and last items
                 tf = uni(tg[0]);
                 const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
@@ -1029,8 +1037,8 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     if (FULL || i < e) out_items[out_rank + i] = y[k];   // serial order
                 }
             }
-            if (!WALK || tf == tl) {
-                if constexpr (WALK) {
+            if (!PERLANE || tf == tl) {
+                if constexpr (PERLANE) {
                     if (tf != utag) {   // every lane's accumulator closes together
                         flush_wave(utag);
                         utag = tf;
@@ -1055,7 +1063,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) acc_add(acc, y[k], (FULL || (uint32_t)k * 64u + t < e) && tg[k] == tl);
                 utag = tl;
-            } else if (!TAG || (tl - tf + 1u) * 8u > e) {
+            } else if (!TAGQ || (tl - tf + 1u) * 8u > e) {
                 // regions of a few items each: each lane flushes where its own items change region
                 // (tags grow along the queue), then every lane flushes at the end
                 uint32_t lt = utag;
@@ -1135,7 +1143,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint32_t pos = (h1 + (uint32_t)k * 64u + t) & (D1 - 1u);
                 x[k] = q1v[pos];
                 if constexpr (KIND == RS_HASH_EXPAND) c[k] = q1a[pos]; else c[k] = 1u;
-                if constexpr (TAG) tg[k] = q1t[pos]; else tg[k] = 0u;
+                if constexpr (TAGQ) tg[k] = q1t[pos]; else tg[k] = 0u;
             }
             // output counts of every round (they do not depend on the word lengths below)
             uint64_t b0[V], b1[V];
@@ -1154,7 +1162,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
                     if (!(FULL || (uint32_t)k * 64u + t < e)) continue;
-                    const uint32_t j = TAG ? tg[k] : ej;
+                    const uint32_t j = TAGQ ? tg[k] : ej;
                     const uint32_t le = SX[j] + (VT[j + 1] - VT[j]);
                     uint32_t p = x[k];
                     while (p < le) {
@@ -1209,7 +1217,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                         const uint32_t pos = pick(m, sl, D2 + t);
                         // child ch of x leaves as its pre-image x ^ K(ch+1) (hash kind); a word as its length
                         q2v[pos] = KIND == RS_HASH_EXPAND ? x[k] ^ salt_key(ch + 1u) : x[k];
-                        if constexpr (TAG) q2t[pos] = (uint8_t)tg[k];
+                        if constexpr (TAGQ) q2t[pos] = (uint8_t)tg[k];
                     }
                     run += (uint32_t)__popcll(b0[k]) + 2u * (uint32_t)__popcll(b1[k]);
                 }
@@ -1288,7 +1296,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint32_t pos = pick(b, (t1 + run + within) & (D1 - 1u), D1 + ((t1 + run + pc + t - within) & 63u));
                 q1v[pos] = item;
                 if constexpr (KIND == RS_HASH_EXPAND) q1a[pos] = (uint8_t)aux;
-                if constexpr (TAG) q1t[pos] = (uint8_t)reg[k];
+                if constexpr (TAGQ) q1t[pos] = (uint8_t)reg[k];
                 run += pc;
             }
             if constexpr (FREG) {
@@ -1490,6 +1498,12 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             h2w = t2w = 0;
             uint32_t lt = 0;   // items at the front of A's queue
             if constexpr (WALK) (void)fuse_walk_region(lt);
+            if constexpr (HYB) {
+                if (utag != fj) {
+                    flush_wave(utag);
+                    utag = fj;
+                }
+            }
             for (;;) {
                 // ---- the ensemble's slot, and the next ensemble's copy into the other slot (both
                 // slots' positions are updated by selects: a conditional store to one or the other
@@ -1523,9 +1537,12 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if constexpr (!WALK) {
                     if (fpos == rend) {
                         // region ja ends: A takes the items before its signal, then ends it
+                        // (per-stage choice: the items are tagged, and A closes the region it holds)
                         fuse_drain(lt);
                         lt = 0;
-                        if (a_items) {
+                        if constexpr (HYB) {
+                            flush_wave(utag);
+                        } else if (a_items) {
                             const Acc r = wave_reduce(acc);
                             if (t == 0) {
                                 s_cnt[ja] = r.cnt;
@@ -1541,13 +1558,16 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                             ++fj;
                             ++ej;
                             ++ja;
-                            stat(ST_SIGNALS + 0, 1u);
-                            stat(ST_SIGNALS + 1, 1u);
-                            stat(ST_SIGNALS + 2, 1u);
+                            if constexpr (!HYB) {
+                                stat(ST_SIGNALS + 0, 1u);
+                                stat(ST_SIGNALS + 1, 1u);
+                                stat(ST_SIGNALS + 2, 1u);
+                            }
                         } while (fj < nb && uni(VT[fj + 1u]) == fpos);
                         fdone = fj == nb;   // (an unconditional store, as for the slots above)
                         if (fdone) break;
                         rend = uni(VT[fj + 1u]);
+                        if constexpr (HYB) utag = fj;
                     }
                     if (fpos + EW > rend) break;
                 } else {
@@ -1557,7 +1577,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             // A's queue holds the leftover in slots [0, lt) for the scheduler
             t2w = lt;
-            if constexpr (TAG) {
+            if constexpr (TAGQ) {
                 if (t < lt) q2t[t] = (uint8_t)utag;
             }
             if constexpr (TAG) {
@@ -1594,7 +1614,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                         continue;
                     }
                 }
-                if constexpr (!WALK) {
+                if constexpr (SIGQ) {
                     uint32_t &sh = HAS_E ? sh2 : sh1;
                     const uint32_t stq = HAS_E ? st2 : st1;
                     if (sh < stq) {
@@ -1667,7 +1687,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                         if (nle > free2) e = __builtin_amdgcn_readlane(sq1, (sh1 + free2) & (SQ - 1u)) - h1;
                     }
                 }
-                if constexpr (!WALK) {
+                if constexpr (SIGQ) {
                     if (sh1 < st1) {
                         pending = true;
                         const uint32_t p = __builtin_amdgcn_readlane(sq1, sh1 & (SQ - 1u));
@@ -1747,16 +1767,19 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint32_t lim = TAG ? vend : rend;
                 const uint32_t e = min(EW, lim - fpos);
                 const bool ends = !TAG && fpos + e == rend;
-                // room for every item (all might pass) and, at a region's end, for its signal
-                if (D1 - (t1 - h1) >= e && (!ends || st1 - sh1 < SQ)) {
+                // room for every item (all might pass) and, at a region's end, for its signal (the
+                // per-stage choice tags instead)
+                if (D1 - (t1 - h1) >= e && (!ends || HYB || st1 - sh1 < SQ)) {
                     if (e == EW) f_node(BoolC<true>{}, e, 0u);
                     else if (e) f_node(BoolC<false>{}, e, 0u);
                     if constexpr (TAG) {
                         fdone = (fpos == vend);
                     } else if (ends) {
-                        sq1 = t == (st1 & (SQ - 1u)) ? t1 : sq1;
-                        ++st1;
-                        stat(ST_SIGNALS + 0, 1u);
+                        if constexpr (!HYB) {
+                            sq1 = t == (st1 & (SQ - 1u)) ? t1 : sq1;
+                            ++st1;
+                            stat(ST_SIGNALS + 0, 1u);
+                        }
                         ++fj;
                         fdone = (fj == nb);
                         if (!fdone) {
@@ -1776,7 +1799,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             break;
         }
 
-        if constexpr (WALK) flush_wave(utag);
+        if constexpr (PERLANE) flush_wave(utag);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no staged copy outlives the claim
         order();
         if (failed && t == 0) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1854,12 +1877,23 @@ static KernelFn pick_lanes(uint32_t w) {
     }
 }
 
+// Enumeration with tags downstream (the per-stage choice): kinds with a second stage.
+template <int KIND>
+static KernelFn pick_enum_tag(uint32_t w) {
+    if constexpr (KIND == RS_HASH_EXPAND || KIND == RS_TEXT_WORDS) {
+        return pick_width<KIND, RS_ENUM_TAG>(w);
+    } else {
+        return nullptr;
+    }
+}
+
 template <int KIND>
 static KernelFn pick_strategy(uint32_t s, uint32_t w) {
     switch (s) {
         case RS_TAG: return pick_width<KIND, RS_TAG>(w);
         case RS_SIGNAL: return pick_width<KIND, RS_SIGNAL>(w);
         case RS_SIGNAL_LANES: return pick_lanes<KIND>(w);
+        case RS_ENUM_TAG: return pick_enum_tag<KIND>(w);
         default: return nullptr;
     }
 }

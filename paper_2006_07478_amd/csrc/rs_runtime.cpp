@@ -326,7 +326,11 @@ void claim_plan(uint32_t kind, bool ordered_out, uint32_t width, uint32_t n_pare
     const double min_claims = ordered_out ? 2048.0 : 8192.0;
     const bool big = kind != RS_TEXT_WORDS && mean_len > 0 && (ordered_out || 32.0 * width / mean_len <= 32.0) &&
                      (double)n_parents * mean_len >= min_claims * 32.0 * width;
-    const double b = mean_len > 0 ? (big ? 32.0 : 16.0) * width / mean_len : bmax;
+    double b = mean_len > 0 ? (big ? 32.0 : 16.0) * width / mean_len : bmax;
+    // text lines hold few second-stage items (word starts) for their bytes: a claim takes at least
+    // 8 lines while that leaves 2048 claims, so that the second stage's ensembles can fill up
+    // across lines where the strategy lets them (tags)
+    if (kind == RS_TEXT_WORDS) b = std::max(b, std::min(8.0, n_parents / 2048.0));
     *B = (uint32_t)std::max(1.0, std::min(bmax, b));
     *n_claims = (uint32_t)(((uint64_t)n_parents + *B - 1) / *B);
 }
@@ -537,7 +541,7 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
     HIP_OR(hipEventCreate(&e0), RS_EDEVICE);
     HIP_OR(hipEventCreate(&e1), RS_EDEVICE);
     int rc = RS_OK;
-    for (uint32_t strat : {(uint32_t)RS_TAG, (uint32_t)RS_SIGNAL, (uint32_t)RS_SIGNAL_LANES}) {
+    for (uint32_t strat : {(uint32_t)RS_TAG, (uint32_t)RS_SIGNAL, (uint32_t)RS_SIGNAL_LANES, (uint32_t)RS_ENUM_TAG}) {
         if (rc != RS_OK) break;
         if (want_s != RS_AUTO && strat != want_s) continue;
         for (uint32_t wq = 0; wq < 2 * (sizeof kWidths / sizeof kWidths[0]) && rc == RS_OK; ++wq) {
@@ -635,7 +639,9 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     if (d->abi_version != RS_ABI_VERSION)
         return fail(RS_EINVAL, "abi_version %u, library is %u", d->abi_version, RS_ABI_VERSION);
     if (d->kind < RS_MODFILTER || d->kind > RS_GRAPH_THRESH) return fail(RS_EINVAL, "unknown kind %u", d->kind);
-    if (d->strategy > RS_SIGNAL_LANES) return fail(RS_EINVAL, "unknown strategy %u", d->strategy);
+    if (d->strategy > RS_ENUM_TAG) return fail(RS_EINVAL, "unknown strategy %u", d->strategy);
+    if (d->strategy == RS_ENUM_TAG && !rs::kernel_supported(d->kind, RS_ENUM_TAG, d->ensemble_width ? d->ensemble_width : 64))
+        return fail(RS_EINVAL, "enumeration with tags downstream is offered for kinds with a second stage");
     if (d->strategy == RS_SIGNAL_LANES && !rs::kernel_supported(d->kind, RS_SIGNAL_LANES, d->ensemble_width ? d->ensemble_width : 64))
         return fail(RS_EINVAL, "lane-resolved signals are offered for u32 kinds only");
     if (d->agg_fields == 0 || (d->agg_fields & ~15u))

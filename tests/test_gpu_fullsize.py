@@ -117,6 +117,30 @@ def test_variable_sizes_2p26(mx):
         check(got, ref, ("count", "sum", "min", "max"), f"2^26 variable max={mx} {SNAME[s]}")
 
 
+def test_taxi_shape_1gib():
+    """The taxi-shaped text at 1 GiB under the three versions of §5 (signals; enumeration then
+    tags; tags)."""
+    text, starts, lengths = workloads.taxi_workload(seed=9, total_bytes=1 << 30)
+    say("taxi 1 GiB:", len(starts), "lines")
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths)
+    for s in (rs.RS_SIGNAL, rs.RS_ENUM_TAG, rs.RS_TAG):
+        say("taxi 1 GiB", s)
+        got, st = run_dev(rs.RS_TEXT_WORDS, s, starts, text, lengths=lengths, fields=rs.RS_COUNT | rs.RS_MAX)
+        check(got, ref, ("count", "max"), f"taxi {s}")
+
+
+def test_enum_tag_2p26():
+    """Enumeration then tags at the headline size, short and long regions."""
+    n = 1 << 26
+    vals = workloads.hash_values(2, n)
+    for L in (16, 4096):
+        offsets = workloads.fixed_offsets(n, L)
+        ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+        say("2^26 enum+tag L", L)
+        got, _ = run_dev(rs.RS_HASH_EXPAND, rs.RS_ENUM_TAG, offsets, vals)
+        check(got, ref, ("count", "sum", "min", "max"), f"2^26 enum+tag L={L}")
+
+
 def test_text_1gib():
     text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 30)
     say("text 1 GiB:", len(starts), "lines")

@@ -17,17 +17,21 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 STRATS = [rs.RS_TAG, rs.RS_SIGNAL]
 # with lane-resolved signals, offered for u32 kinds at widths up to 256
 ALL3 = STRATS + [rs.RS_SIGNAL_LANES]
-SNAME = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal", rs.RS_SIGNAL_LANES: "lanes"}
+SNAME = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal", rs.RS_SIGNAL_LANES: "lanes", rs.RS_ENUM_TAG: "enum+tag"}
 
 
 def strats(kind, width):
     """The strategies offered for a kind and an ensemble width."""
-    return ALL3 if kind != rs.RS_TEXT_WORDS and width <= 256 else STRATS
+    out = ALL3 if kind != rs.RS_TEXT_WORDS and width <= 256 else STRATS
+    if kind in (rs.RS_HASH_EXPAND, rs.RS_TEXT_WORDS):   # enumeration, then tags: kinds with a second stage
+        out = out + [rs.RS_ENUM_TAG]
+    return out
 
 
 def skip_unoffered(kind, strategy, width):
     if strategy not in strats(kind, width):
-        pytest.skip("lane-resolved signals are offered for u32 kinds at widths up to 256")
+        pytest.skip("lane-resolved signals are offered for u32 kinds at widths up to 256, enumeration "
+                    "with tags downstream for kinds with a second stage")
 ALL = rs.RS_COUNT | rs.RS_SUM | rs.RS_MIN | rs.RS_MAX
 WIDTHS = [64, 128, 256, 512, 1024]
 
@@ -502,7 +506,7 @@ _CAND = {}
 
 
 @pytest.mark.parametrize("width", WIDTHS)
-@pytest.mark.parametrize("strategy", ALL3)
+@pytest.mark.parametrize("strategy", ALL3 + [rs.RS_ENUM_TAG])
 @pytest.mark.parametrize("kind", [rs.RS_MODFILTER, rs.RS_HASH_EXPAND, rs.RS_TEXT_WORDS, rs.RS_GRAPH_THRESH])
 def test_every_autotune_candidate(kind, strategy, width):
     """Each (kind, strategy, width) that RS_AUTO may select, against the oracle (§3.3: the SIMD rule
@@ -522,7 +526,7 @@ def test_every_autotune_candidate(kind, strategy, width):
 
 @pytest.mark.parametrize("factor", [4, 8])
 @pytest.mark.parametrize("width", [64, 256])
-@pytest.mark.parametrize("strategy", ALL3)
+@pytest.mark.parametrize("strategy", ALL3 + [rs.RS_ENUM_TAG])
 @pytest.mark.parametrize("kind", [rs.RS_MODFILTER, rs.RS_HASH_EXPAND, rs.RS_TEXT_WORDS, rs.RS_GRAPH_THRESH])
 def test_queue_depths(kind, strategy, width, factor):
     """Queue depths 4w and 8w (every other test runs the default 2w; the autotuner picks 2w or 4w)
@@ -632,3 +636,89 @@ def test_kernel_times_cover_every_timed_launch():
         with pytest.raises(rs.RsError) as ei:
             p.kernel_times()
         assert ei.value.code == rs.RS_EINVAL
+
+
+# ---- per-stage choice: enumeration in the first stage, tags after it (the second taxi version) ----
+
+@pytest.mark.parametrize("L", [1, 4, 16, 64, 256, 1024, 4096])
+def test_enum_tag_hash_fixed_L(L):
+    n = (1 << 18) + 13
+    say("enum+tag hash/expand L", L)
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    got, st = run_one(rs.RS_HASH_EXPAND, rs.RS_ENUM_TAG, 256, offsets, vals, flags=rs.RS_COLLECT_STATS)
+    check(got, ref, where=f"enum+tag L={L}")
+    # the enumerating node's ensembles stop at region ends, as under signals; no signal travels
+    assert st.items[0] == n and st.firings[0] >= len(offsets) - 1
+    assert sum(st.signals) == 0
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_enum_tag_widths(width):
+    say("enum+tag widths", width)
+    offsets = workloads.uniform_offsets(5, 3000, 300)
+    vals = workloads.hash_values(5, int(offsets[-1]))
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
+    got, _ = run_one(rs.RS_HASH_EXPAND, rs.RS_ENUM_TAG, width, offsets, vals)
+    check(got, ref, where=f"enum+tag hash width {width}")
+    text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 20)
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths)
+    got, _ = run_one(rs.RS_TEXT_WORDS, rs.RS_ENUM_TAG, width, starts, text, lengths=lengths)
+    check(got, ref, ("count", "max"), where=f"enum+tag text width {width}")
+
+
+@pytest.mark.parametrize("name", ["e2_hash_expand.json", "e3_text_words.json"])
+@pytest.mark.parametrize("width", [64, 256])
+def test_enum_tag_golden_streams(name, width):
+    test_golden_streams(name, rs.RS_ENUM_TAG, width)
+
+
+def test_enum_tag_edge_cases():
+    say("enum+tag edge cases")
+    offs = np.zeros(1001, np.uint32)
+    got, _ = run_one(rs.RS_HASH_EXPAND, rs.RS_ENUM_TAG, 256, offs, np.zeros(4, np.uint32))
+    assert (got["count"] == 0).all() and (got["min"] == 0xFFFFFFFF).all() and (got["max"] == 0).all()
+    vals = workloads.hash_values(3, 200003)
+    offs = np.array([0, 200003], np.uint32)
+    check(run_one(rs.RS_HASH_EXPAND, rs.RS_ENUM_TAG, 256, offs, vals)[0], oracle.run(oracle.HASH_EXPAND, offs, vals),
+          where="enum+tag one parent")
+    vals = workloads.hash_values(4, 5000)
+    offs = np.array([7, 7, 100, 2500, 4990], np.uint32)
+    check(run_one(rs.RS_HASH_EXPAND, rs.RS_ENUM_TAG, 128, offs, vals)[0], oracle.run(oracle.HASH_EXPAND, offs, vals),
+          where="enum+tag offset start")
+
+
+@pytest.mark.parametrize("L", [1, 7, 300, 5000])
+def test_enum_tag_output_stream(L):
+    say("enum+tag outputs", L)
+    n = 150001
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(9, n)
+    ref = oracle.run(oracle.HASH_EXPAND, offsets, vals, emit_outputs=True)
+    got, out = run_outputs(rs.RS_HASH_EXPAND, rs.RS_ENUM_TAG, 256, offsets, vals)
+    check(got, ref, where="enum+tag outputs agg")
+    assert len(out) == len(ref.out) and np.array_equal(out, ref.out)
+    text, starts, lengths = workloads.text_workload(seed=3, total_bytes=1 << 19)
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths, emit_outputs=True)
+    _, out = run_outputs(rs.RS_TEXT_WORDS, rs.RS_ENUM_TAG, 256, starts, text, lengths=lengths)
+    assert np.array_equal(out, ref.out)
+
+
+@pytest.mark.parametrize("width", [64, 128, 256])
+def test_taxi_shape_three_versions(width):
+    """The paper's three taxi versions on taxi-shaped text (lines of 1397 characters on average,
+    about 45 markers each): both stages enumerated (signals), the first enumerated and tags
+    after it, neither enumerated (tags).  Each equals the oracle; the first stage's full-ensemble
+    share is high under enumeration and the second's is low under signals only."""
+    text, starts, lengths = workloads.taxi_workload(seed=9, total_bytes=1 << 23)
+    ref = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths)
+    full = {}
+    for s in (rs.RS_SIGNAL, rs.RS_ENUM_TAG, rs.RS_TAG):
+        say("taxi", SNAME[s], width)
+        got, st = run_one(rs.RS_TEXT_WORDS, s, width, starts, text, lengths=lengths, fields=rs.RS_COUNT | rs.RS_MAX,
+                          flags=rs.RS_COLLECT_STATS)
+        check(got, ref, ("count", "max"), where=f"taxi {SNAME[s]} w={width}")
+        full[s] = [st.full[k] / max(1, st.firings[k]) for k in range(3)]
+    assert full[rs.RS_SIGNAL][0] > 0.5 and full[rs.RS_ENUM_TAG][0] > 0.5     # stage 1: long regions
+    assert full[rs.RS_ENUM_TAG][1] > full[rs.RS_SIGNAL][1]                  # stage 2: tags fill ensembles

@@ -91,3 +91,14 @@ def test_variable_offsets_cover_exactly_n():
             assert abs(d[:-1].mean() - mx / 2) < 0.05 * mx + 0.05
     e = W.variable_offsets(3, 1000, 0)
     assert len(e) == 4097 and not e.any()
+
+
+def test_taxi_shape():
+    """The taxi-shaped text: mean line length near 1397 characters and about 45 markers (word
+    starts) per line, the two figures the paper gives for its second application (§5)."""
+    import oracle
+    text, starts, lengths = W.taxi_workload(seed=9, total_bytes=1 << 24)
+    assert abs(float(lengths.mean()) / W.TAXI_MEAN_LINE - 1.0) < 0.06
+    assert text[-1] == ord("\n") and len(text) == 1 << 24
+    words = oracle.run(oracle.TEXT_WORDS, starts, text, lengths=lengths).count
+    assert abs(float(words.mean()) / 45.0 - 1.0) < 0.08

@@ -149,6 +149,21 @@ def text_workload(seed=3, total_bytes=1 << 30, mean_len=80.0, max_len=65536, spa
     return text[:total_bytes], starts[:n_lines], lengths[:n_lines]
 
 
+# The shape of the paper's second application (§5): long lines (1397 characters on average)
+# holding about 45 markers each, a marker being where a word starts.  A line is geometric in
+# length with that mean; a byte is a space with probability 2195/65536, so a line of L bytes
+# holds about L p (1 - p) = 45 words.  Synthetic bytes only: no record of the application's
+# input is used.
+TAXI_MEAN_LINE = 1397.0
+TAXI_SPACE_PER_65536 = 2195
+
+
+def taxi_workload(seed=9, total_bytes=1 << 30):
+    """Returns (text, line starts, line lengths) shaped like the paper's taxi input."""
+    return text_workload(seed=seed, total_bytes=total_bytes, mean_len=TAXI_MEAN_LINE, max_len=65536,
+                         space_per_65536=TAXI_SPACE_PER_65536)
+
+
 # ---- edges grouped by source vertex ----
 
 def graph_offsets(seed=4, n_vertices=1 << 24, n_edges=1 << 28, alpha=1.1, cap=100000):
