@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
-MODFILTER, HASH_EXPAND, TEXT_WORDS, GRAPH_THRESH = 1, 2, 3, 4
+MODFILTER, HASH_EXPAND, TEXT_WORDS, GRAPH_THRESH, HASH_TREE = 1, 2, 3, 4, 5
 
 _lib = None
 
@@ -50,6 +50,10 @@ def lib():
         L.oracle_run.argtypes = [ctypes.c_int, u32p, ctypes.c_uint64, u32p, u32p, ctypes.c_void_p,
                                  ctypes.c_uint64, u32p, u32p, u64p, u32p, u32p, u32p,
                                  ctypes.c_uint64, u64p]
+        L.oracle_run_tree.restype = ctypes.c_int
+        L.oracle_run_tree.argtypes = [ctypes.c_int, u32p, ctypes.c_uint64, u32p, u32p, ctypes.c_void_p,
+                                      ctypes.c_uint64, u32p, u32p, u64p, u32p, u32p, u32p, u64p, u32p,
+                                      ctypes.c_uint64, u64p]
         L.oracle_fmix32.restype = ctypes.c_uint32
         L.oracle_fmix32.argtypes = [ctypes.c_uint32]
         L.oracle_hash.restype = ctypes.c_uint32
@@ -65,10 +69,12 @@ def _ptr(a, ctype):
 
 
 class Result:
-    """Per-parent aggregates (structure of arrays) plus the optional surviving-item stream."""
+    """Per-parent aggregates (structure of arrays) plus the optional surviving-item stream; for
+    the tree kind also the second sink's kept_count and kept_sum."""
 
-    def __init__(self, count, sum_, min_, max_, out):
+    def __init__(self, count, sum_, min_, max_, out, kept_count=None, kept_sum=None):
         self.count, self.sum, self.min, self.max, self.out = count, sum_, min_, max_, out
+        self.kept_count, self.kept_sum = kept_count, kept_sum
 
     def __repr__(self):
         return f"Result(count={self.count}, sum={self.sum}, min={self.min}, max={self.max}, out={self.out})"
@@ -79,7 +85,7 @@ def run(kind, offsets, elements, lengths=None, parent_param=None, param=(0, 0, 0
     """Run the serial oracle.
 
     offsets: CSR offsets [P+1] (lengths None) or region starts [P] (lengths given).
-    elements: uint32 array (kinds 1, 2, 4) or uint8 array (kind 3).
+    elements: uint32 array (kinds 1, 2, 4, 5) or uint8 array (kind 3).
     Returns a Result with count/sum/min/max arrays and, if asked, the output stream.
     """
     offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
@@ -113,16 +119,21 @@ def run(kind, offsets, elements, lengths=None, parent_param=None, param=(0, 0, 0
             raise ValueError(f"oracle_run failed: {rc}")
         cap = n_out.value
         out = np.zeros(max(cap, 1), np.uint32)
-    rc = L.oracle_run(kind, _ptr(prm, ctypes.c_uint32), n_par, _ptr(offsets, ctypes.c_uint32),
-                      _ptr(lengths, ctypes.c_uint32), elements.ctypes.data, len(elements),
-                      _ptr(parent_param, ctypes.c_uint32), _ptr(count, ctypes.c_uint32),
-                      _ptr(sum_, ctypes.c_uint64), _ptr(mn, ctypes.c_uint32), _ptr(mx, ctypes.c_uint32),
-                      _ptr(out, ctypes.c_uint32), cap, ctypes.byref(n_out))
+    kc = ks = None
+    if kind == HASH_TREE:
+        kc = np.zeros(n_par, np.uint32)
+        ks = np.zeros(n_par, np.uint64)
+    rc = L.oracle_run_tree(kind, _ptr(prm, ctypes.c_uint32), n_par, _ptr(offsets, ctypes.c_uint32),
+                           _ptr(lengths, ctypes.c_uint32), elements.ctypes.data, len(elements),
+                           _ptr(parent_param, ctypes.c_uint32), _ptr(count, ctypes.c_uint32),
+                           _ptr(sum_, ctypes.c_uint64), _ptr(mn, ctypes.c_uint32), _ptr(mx, ctypes.c_uint32),
+                           _ptr(kc, ctypes.c_uint32), _ptr(ks, ctypes.c_uint64),
+                           _ptr(out, ctypes.c_uint32), cap, ctypes.byref(n_out))
     if rc != 0:
         raise ValueError(f"oracle_run failed: {rc}")
     if out is not None:
         out = out[:n_out.value].copy()
-    return Result(count, sum_, mn, mx, out)
+    return Result(count, sum_, mn, mx, out, kc, ks)
 
 
 def fmix32(x):

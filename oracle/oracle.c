@@ -35,6 +35,7 @@
 #define OR_HASH_EXPAND  2
 #define OR_TEXT_WORDS   3
 #define OR_GRAPH_THRESH 4
+#define OR_HASH_TREE    5
 
 #define OR_OK     0
 #define OR_EINVAL (-1)
@@ -106,11 +107,14 @@ static void sink_item(or_sink *s, uint32_t y)
 /*
  * Run one element (enumeration index i of parent p, whose region holds
  * n_p elements starting at 'base') through the stages of 'kind', feeding
- * every surviving item, in order, to the aggregating node.
+ * every surviving item, in order, to the aggregating node.  A tree
+ * (OR_HASH_TREE, the tree topologies of §2.1) also feeds a second sink
+ * 'second': the filter stage has two children, the expansion (whose
+ * outputs reach the first sink) and an aggregating node of its own.
  */
 static void run_stages(int kind, const uint32_t *param, const void *elements,
                        uint64_t base, uint32_t n_p, uint32_t i,
-                       uint32_t ctx, or_sink *s)
+                       uint32_t ctx, or_sink *s, or_acc *second)
 {
     if (kind == OR_MODFILTER) {
         /* Stage 1 (k = 1): keep x when x mod m equals r. */
@@ -118,11 +122,13 @@ static void run_stages(int kind, const uint32_t *param, const void *elements,
         uint32_t m = param[0] ? param[0] : 4u;
         uint32_t r = param[1];
         if (x % m == r) sink_item(s, x);
-    } else if (kind == OR_HASH_EXPAND) {
+    } else if (kind == OR_HASH_EXPAND || kind == OR_HASH_TREE) {
         /* Stage 1 (k = 1): keep x when bit 0 of H(x,0) is set. */
         uint32_t x = ((const uint32_t *)elements)[base + i];
         uint32_t h = or_hash(x, 0);
         if (h & 1u) {
+            /* The tree's second child of stage 1 aggregates the survivor itself. */
+            if (kind == OR_HASH_TREE) acc_run(second, x);
             /* Stage 2 (k = 3): emit c = bits 1..2 of H(x,0) children H(x, j+1), j ascending. */
             uint32_t c = (h >> 1) & 3u;
             for (uint32_t j = 0; j < c; ++j) sink_item(s, or_hash(x, j + 1u));
@@ -151,7 +157,7 @@ static void run_stages(int kind, const uint32_t *param, const void *elements,
  *   n_parents     number of parents P
  *   offsets       lengths == NULL: CSR offsets[P+1], region p = [offsets[p], offsets[p+1])
  *                 lengths != NULL: starts[P],     region p = [offsets[p], offsets[p]+lengths[p])
- *   elements      u32 array (kinds 1, 2, 4) or byte array (kind 3) of n_elements entries
+ *   elements      u32 array (kinds 1, 2, 4, 5) or byte array (kind 3) of n_elements entries
  *   parent_param  per-parent context (kind 4: threshold), else NULL
  *   count/sum/min/max   per-parent outputs [P], NULL to skip a field
  *   out, out_cap  optional surviving-item stream in serial order; n_out gets its length
@@ -159,21 +165,23 @@ static void run_stages(int kind, const uint32_t *param, const void *elements,
  * Returns OR_OK, OR_EINVAL on a region outside the element array, or OR_ECAP when
  * out_cap is too small (n_out still reports the full length).
  */
-int oracle_run(int kind, const uint32_t *param, uint64_t n_parents,
-               const uint32_t *offsets, const uint32_t *lengths,
-               const void *elements, uint64_t n_elements,
-               const uint32_t *parent_param,
-               uint32_t *count, uint64_t *sum, uint32_t *min, uint32_t *max,
-               uint32_t *out, uint64_t out_cap, uint64_t *n_out)
+static int run_all(int kind, const uint32_t *param, uint64_t n_parents,
+                   const uint32_t *offsets, const uint32_t *lengths,
+                   const void *elements, uint64_t n_elements,
+                   const uint32_t *parent_param,
+                   uint32_t *count, uint64_t *sum, uint32_t *min, uint32_t *max,
+                   uint32_t *kcount, uint64_t *ksum,
+                   uint32_t *out, uint64_t out_cap, uint64_t *n_out)
 {
     static const uint32_t zero_param[4] = {0, 0, 0, 0};
     or_sink s;
+    or_acc second;
     s.out = out;
     s.out_cap = out_cap;
     s.n_out = 0;
     s.overflow = 0;
     if (!param) param = zero_param;
-    if (kind < OR_MODFILTER || kind > OR_GRAPH_THRESH) return OR_EINVAL;
+    if (kind < OR_MODFILTER || kind > OR_HASH_TREE) return OR_EINVAL;
     if (kind == OR_GRAPH_THRESH && !parent_param && n_parents) return OR_EINVAL;
 
     for (uint64_t p = 0; p < n_parents; ++p) {            /* parents in stream order */
@@ -183,13 +191,44 @@ int oracle_run(int kind, const uint32_t *param, uint64_t n_parents,
         uint32_t n_p = (uint32_t)(end - base);             /* findCount() */
         uint32_t ctx = parent_param ? parent_param[p] : 0; /* getParent() context */
         acc_begin(&s.acc);                                 /* begin() */
+        acc_begin(&second);
         for (uint32_t i = 0; i < n_p; ++i)                 /* enumeration index order */
-            run_stages(kind, param, elements, base, n_p, i, ctx, &s);
+            run_stages(kind, param, elements, base, n_p, i, ctx, &s, &second);
         if (count) count[p] = s.acc.count;                 /* end(): one record per parent */
         if (sum) sum[p] = s.acc.sum;
         if (min) min[p] = s.acc.min;
         if (max) max[p] = s.acc.max;
+        if (kcount) kcount[p] = second.count;              /* the second sink's record */
+        if (ksum) ksum[p] = second.sum;
     }
     if (n_out) *n_out = s.n_out;
     return s.overflow ? OR_ECAP : OR_OK;
+}
+
+int oracle_run(int kind, const uint32_t *param, uint64_t n_parents,
+               const uint32_t *offsets, const uint32_t *lengths,
+               const void *elements, uint64_t n_elements,
+               const uint32_t *parent_param,
+               uint32_t *count, uint64_t *sum, uint32_t *min, uint32_t *max,
+               uint32_t *out, uint64_t out_cap, uint64_t *n_out)
+{
+    return run_all(kind, param, n_parents, offsets, lengths, elements, n_elements, parent_param,
+                   count, sum, min, max, NULL, NULL, out, out_cap, n_out);
+}
+
+/*
+ * oracle_run_tree: as oracle_run, plus the records of the tree's second sink
+ * (OR_HASH_TREE): per parent, the count and the sum of the elements that pass
+ * the filter stage.
+ */
+int oracle_run_tree(int kind, const uint32_t *param, uint64_t n_parents,
+                    const uint32_t *offsets, const uint32_t *lengths,
+                    const void *elements, uint64_t n_elements,
+                    const uint32_t *parent_param,
+                    uint32_t *count, uint64_t *sum, uint32_t *min, uint32_t *max,
+                    uint32_t *kcount, uint64_t *ksum,
+                    uint32_t *out, uint64_t out_cap, uint64_t *n_out)
+{
+    return run_all(kind, param, n_parents, offsets, lengths, elements, n_elements, parent_param,
+                   count, sum, min, max, kcount, ksum, out, out_cap, n_out);
 }

@@ -12,7 +12,7 @@ every region, so every parent gets one record.
 MASK32 = 0xFFFFFFFF
 MASK64 = 0xFFFFFFFFFFFFFFFF
 
-MODFILTER, HASH_EXPAND, TEXT_WORDS, GRAPH_THRESH = 1, 2, 3, 4
+MODFILTER, HASH_EXPAND, TEXT_WORDS, GRAPH_THRESH, HASH_TREE = 1, 2, 3, 4, 5
 
 
 def murmur_fmix32(h):
@@ -94,3 +94,24 @@ def run(kind, offsets, elements, lengths=None, parent_param=None, param=(0, 0, 0
         else:
             records.append((0, 0, MASK32, 0))
     return records, outputs
+
+
+def run_tree(offsets, elements):
+    """The tree topology of §2.1 on the hash stages: the filter's survivors go both to the
+    expansion, whose children reach the first sink, and to a second sink of their own.  Returns
+    (records, second, outputs): records[p] = (count, sum, min, max) of the children,
+    second[p] = (count, sum) of the survivors, outputs the children in serial order."""
+    keep, expand = stages_for(HASH_EXPAND)
+    records, second, outputs = [], [], []
+    for s, e in regions(offsets):
+        kids, kept = [], []
+        for i in range(e - s):
+            survivors = keep(int(elements[s + i]), None)
+            kept.extend(survivors)
+            for x in survivors:
+                kids.extend(expand(x, None))
+        outputs.extend(kids)
+        records.append((len(kids) & MASK32, sum(kids) & MASK64, min(kids), max(kids)) if kids
+                       else (0, 0, MASK32, 0))
+        second.append((len(kept) & MASK32, sum(kept) & MASK64))
+    return records, second, outputs

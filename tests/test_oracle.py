@@ -383,3 +383,57 @@ def test_planted_mistakes_are_caught():
         assert not _golden_agrees(mutant), mutant.__name__
     # a wrong identity for empty regions is caught too
     assert not _golden_agrees(lambda orig: orig, agg_identity=(0, 0, 0, 0))
+
+
+# ---- tree topology (§2.1): the filter feeds the expansion and a second sink ----
+
+def test_tree_first_sink_is_the_linear_pipeline():
+    """The tree's first sink sees exactly the linear pipeline's items: its records and output
+    stream equal the hash/expand oracle's (the pinned linear case)."""
+    offsets = workloads.uniform_offsets(41, 700, 60)
+    vals = workloads.hash_values(41, int(offsets[-1]))
+    t = oracle.run(oracle.HASH_TREE, offsets, vals, emit_outputs=True)
+    h = oracle.run(oracle.HASH_EXPAND, offsets, vals, emit_outputs=True)
+    for f in ("count", "sum", "min", "max", "out"):
+        assert np.array_equal(getattr(t, f), getattr(h, f)), f
+
+
+def test_tree_second_sink_matches_vectorized_numpy():
+    """The second sink holds, per region, the count and the sum of the elements whose H(x,0) has
+    bit 0 set: a numpy replay of the hash (written here) and bincount with int64 sums."""
+    offsets = workloads.uniform_offsets(42, 900, 40)
+    vals = workloads.hash_values(42, int(offsets[-1]))
+    t = oracle.run(oracle.HASH_TREE, offsets, vals)
+    keep = (numpy_hash(vals, 0) & np.uint64(1)).astype(bool)
+    parent = np.repeat(np.arange(900), np.diff(offsets.astype(np.int64)))
+    assert np.array_equal(t.kept_count, np.bincount(parent[keep], minlength=900))
+    sums = np.bincount(parent[keep], weights=None, minlength=900) * 0
+    np.add.at(sums, parent[keep], vals[keep].astype(np.int64))
+    assert np.array_equal(t.kept_sum.astype(np.int64), sums)
+    # invariants: survivors never exceed the region, children never exceed three per survivor
+    sizes = np.diff(offsets.astype(np.int64))
+    assert (t.kept_count <= sizes).all() and (t.count <= 3 * t.kept_count.astype(np.int64)).all()
+
+
+def test_tree_c_and_tiny_oracles_agree():
+    rng = random.Random(7)
+    for _ in range(30):
+        P = rng.randrange(0, 20)
+        sizes = [rng.choice([0, 1, 2, 5, 17, 40]) for _ in range(P)]
+        offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+        vals = np.array([rng.getrandbits(32) for _ in range(int(offsets[-1]))], np.uint32)
+        t = oracle.run(oracle.HASH_TREE, offsets, vals, emit_outputs=True)
+        recs, second, outs = tiny.run_tree(offsets, vals)
+        assert [tuple(int(v) for v in r) for r in zip(t.count, t.sum, t.min, t.max)] == recs
+        assert [(int(c), int(s)) for c, s in zip(t.kept_count, t.kept_sum)] == second
+        assert t.out.tolist() == outs
+
+
+def test_tree_planted_mistake_is_caught():
+    """A second sink that takes every element instead of the filter's survivors differs from the
+    oracle on a seeded stream."""
+    offsets = workloads.uniform_offsets(43, 200, 30)
+    vals = workloads.hash_values(43, int(offsets[-1]))
+    t = oracle.run(oracle.HASH_TREE, offsets, vals)
+    wrong = [(e - s) for s, e in tiny.regions(offsets)]
+    assert [int(c) for c in t.kept_count] != wrong
