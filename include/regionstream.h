@@ -74,11 +74,18 @@ enum rs_strategy { RS_TAG = 0, RS_SIGNAL = 1, RS_AUTO = 2, RS_SIGNAL_LANES = 3, 
  *                   start or after ' '), then map each start to its word length (k = 1, 1).
  *   RS_GRAPH_THRESH u32 edge weights grouped by source vertex; keep w < parent_param[src]
  *                   (strict); k = 1.
+ *   RS_HASH_TREE    the stages of RS_HASH_EXPAND in a tree topology (§2.1, Fig. 1b): the filter
+ *                   has two children, the expansion (whose children reach the aggregating node
+ *                   of count/sum/min/max) and a second aggregating node that takes the filter's
+ *                   survivors themselves (RS_KEPT_COUNT, RS_KEPT_SUM).  Region boundaries reach
+ *                   both children as the strategy carries them.
  * The item that reaches aggregation is x, the child value, the word length or w. */
-enum rs_kind { RS_MODFILTER = 1, RS_HASH_EXPAND = 2, RS_TEXT_WORDS = 3, RS_GRAPH_THRESH = 4 };
+enum rs_kind { RS_MODFILTER = 1, RS_HASH_EXPAND = 2, RS_TEXT_WORDS = 3, RS_GRAPH_THRESH = 4, RS_HASH_TREE = 5 };
 
-/* Aggregate fields; identities for a region without survivors: 0, 0, 0xFFFFFFFF, 0. */
-enum rs_aggf { RS_COUNT = 1, RS_SUM = 2, RS_MIN = 4, RS_MAX = 8 };
+/* Aggregate fields; identities for a region without survivors: 0, 0, 0xFFFFFFFF, 0.  The last two
+ * are the second sink of RS_HASH_TREE: per region, how many elements pass the filter and their
+ * sum (u64). */
+enum rs_aggf { RS_COUNT = 1, RS_SUM = 2, RS_MIN = 4, RS_MAX = 8, RS_KEPT_COUNT = 16, RS_KEPT_SUM = 32 };
 
 enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
 
@@ -170,6 +177,8 @@ typedef struct {
     uint64_t *sum;
     uint32_t *min;
     uint32_t *max;
+    uint32_t *kept_count;   /* RS_HASH_TREE's second sink */
+    uint64_t *kept_sum;
 } rs_agg_view;
 
 /* Device counters of one stream (RS_COLLECT_STATS).  Node 0 is the enumerated first stage,

@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(HERE, "libregionstream.so")
 ABI_VERSION = 1
 RS_OK, RS_EINVAL, RS_ENOMEM, RS_EDEVICE, RS_EBUDGET, RS_ENOTREADY, RS_ESTATE, RS_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 RS_TAG, RS_SIGNAL, RS_AUTO, RS_SIGNAL_LANES, RS_ENUM_TAG = 0, 1, 2, 3, 4
-RS_MODFILTER, RS_HASH_EXPAND, RS_TEXT_WORDS, RS_GRAPH_THRESH = 1, 2, 3, 4
-RS_COUNT, RS_SUM, RS_MIN, RS_MAX = 1, 2, 4, 8
+RS_MODFILTER, RS_HASH_EXPAND, RS_TEXT_WORDS, RS_GRAPH_THRESH, RS_HASH_TREE = 1, 2, 3, 4, 5
+RS_COUNT, RS_SUM, RS_MIN, RS_MAX, RS_KEPT_COUNT, RS_KEPT_SUM = 1, 2, 4, 8, 16, 32
 RS_MEM_HOST, RS_MEM_DEVICE = 0, 1
 RS_RUN_SYNC, RS_RUN_ASYNC, RS_RUN_PER_STREAM = 0, 1, 2
 RS_READ_BLOCK, RS_NONBLOCK, RS_READ_DEVICE, RS_READ_RELEASE = 0, 1, 2, 4
@@ -54,7 +54,7 @@ class rs_stream_desc(ctypes.Structure):
 
 class rs_agg_view(ctypes.Structure):
     _fields_ = [("count", ctypes.c_void_p), ("sum", ctypes.c_void_p), ("min", ctypes.c_void_p),
-                ("max", ctypes.c_void_p)]
+                ("max", ctypes.c_void_p), ("kept_count", ctypes.c_void_p), ("kept_sum", ctypes.c_void_p)]
 
 
 class rs_stats_t(ctypes.Structure):
@@ -203,10 +203,11 @@ def _ptr(x):
 
 
 FIELDS = (("count", RS_COUNT, np.uint32), ("sum", RS_SUM, np.uint64), ("min", RS_MIN, np.uint32),
-          ("max", RS_MAX, np.uint32))
+          ("max", RS_MAX, np.uint32), ("kept_count", RS_KEPT_COUNT, np.uint32), ("kept_sum", RS_KEPT_SUM, np.uint64))
 
 DEFAULT_FIELDS = {RS_MODFILTER: RS_COUNT | RS_SUM, RS_HASH_EXPAND: RS_COUNT | RS_SUM | RS_MIN | RS_MAX,
-                  RS_TEXT_WORDS: RS_COUNT | RS_MAX, RS_GRAPH_THRESH: RS_COUNT | RS_SUM}
+                  RS_TEXT_WORDS: RS_COUNT | RS_MAX, RS_GRAPH_THRESH: RS_COUNT | RS_SUM,
+                  RS_HASH_TREE: RS_COUNT | RS_SUM | RS_MIN | RS_MAX | RS_KEPT_COUNT | RS_KEPT_SUM}
 
 
 class Pipeline:

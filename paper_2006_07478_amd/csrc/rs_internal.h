@@ -37,6 +37,8 @@ struct StreamDev {
     unsigned long long *agg_sum;
     uint32_t *agg_min;
     uint32_t *agg_max;
+    uint32_t *agg_kcount;          // tree: the second sink's count and sum, or nullptr
+    unsigned long long *agg_ksum;
     uint32_t *out_items;           // ordered output stream or nullptr
     unsigned long long *lookback;  // per-claim look-back words (emit_outputs) or nullptr
     unsigned long long *stats;     // ST_WORDS counters or nullptr
@@ -69,7 +71,8 @@ struct LaunchArgs {
 constexpr uint32_t NOALLOC_MAX_STREAMS = 16;
 constexpr uint32_t NOALLOC_CTL_OFF = 0;
 constexpr uint32_t NOALLOC_TABLE_OFF = 8448;   // CTL_WORDS * 4, a multiple of 256
-constexpr uint32_t NOALLOC_STATS_OFF = NOALLOC_TABLE_OFF + NOALLOC_MAX_STREAMS * 128;
+constexpr uint32_t NOALLOC_TABLE_STRIDE = 256;   // bytes reserved per table entry (sizeof(StreamDev) at most)
+constexpr uint32_t NOALLOC_STATS_OFF = NOALLOC_TABLE_OFF + NOALLOC_MAX_STREAMS * NOALLOC_TABLE_STRIDE;
 constexpr uint32_t NOALLOC_SCRATCH_BYTES = NOALLOC_STATS_OFF + NOALLOC_MAX_STREAMS * 16 * 8;
 struct NoallocTable {
     StreamDev s[NOALLOC_MAX_STREAMS];

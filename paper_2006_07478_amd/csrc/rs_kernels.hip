@@ -347,8 +347,12 @@ struct Geo {
 // q, and one ensemble more behind the expansion (its consumer drains it below one ensemble
 // before the expansion fires, so room for one full ensemble's worst case of 3w on top lets the
 // expansion always fire full ensembles; at q = 2w that is the 3w of that argument).
+// The hash stages, linear (RS_HASH_EXPAND) or in the tree whose filter also feeds a second sink
+// (RS_HASH_TREE).
+__host__ __device__ inline bool hash_kind(uint32_t kind) { return kind == RS_HASH_EXPAND || kind == RS_HASH_TREE; }
+
 __host__ __device__ inline uint32_t depth2(uint32_t kind, uint32_t ew, uint32_t q) {
-    return kind == RS_HASH_EXPAND ? q + ew : kind == RS_TEXT_WORDS ? q : 1u;
+    return hash_kind(kind) ? q + ew : kind == RS_TEXT_WORDS ? q : 1u;
 }
 
 // LDS arrays sized at launch: the data queues (for the queue depth q), each followed by 64
@@ -357,18 +361,20 @@ __host__ __device__ inline uint32_t depth2(uint32_t kind, uint32_t ew, uint32_t 
 // 3w + 66 slots (a leftover of under 64 items, up to 3w children and two slots a firing may write
 // past its last child) followed by 66 dump slots.
 struct Dyn {
-    uint32_t q1v, q2v, q1a, q1t, q2t, sum, vt, sx, cx, cnt, mn, mx, bytes;
+    uint32_t q1v, q2v, q1a, q1t, q2t, sum, ksum, vt, sx, cx, cnt, mn, mx, kcnt, bytes;
 };
 __host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t strategy, uint32_t ew, uint32_t q, uint32_t bmax) {
     const bool tag = strategy == RS_TAG || strategy == RS_ENUM_TAG;   // items carry tags
-    const bool has_e = kind == RS_HASH_EXPAND || kind == RS_TEXT_WORDS;
+    const bool has_e = hash_kind(kind) || kind == RS_TEXT_WORDS;
     const uint32_t d2 = depth2(kind, ew, q);
     uint32_t q2 = has_e ? d2 + 64u : 0u;
-    if (kind == RS_HASH_EXPAND && q2 < 3u * ew + 132u) q2 = 3u * ew + 132u;
+    if (hash_kind(kind) && q2 < 3u * ew + 132u) q2 = 3u * ew + 132u;
     Dyn d;
     uint32_t o = 0;
     d.sum = o;
     o += 8u * bmax;   // u64 slots first (8-byte aligned)
+    d.ksum = o;       // the tree's second sink
+    if (kind == RS_HASH_TREE) o += 8u * bmax;
     d.q1v = o;
     o += 4u * (q + 64u);
     d.q2v = o;
@@ -385,8 +391,10 @@ __host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t strategy, uint
     o += 4u * bmax;
     d.mx = o;
     o += 4u * bmax;
+    d.kcnt = o;
+    if (kind == RS_HASH_TREE) o += 4u * bmax;
     d.q1a = o;
-    if (kind == RS_HASH_EXPAND) o += q + 64u;
+    if (hash_kind(kind)) o += q + 64u;
     d.q1t = o;
     if (tag) o += q + 64u;
     d.q2t = o;
@@ -403,8 +411,8 @@ __host__ __device__ inline Dyn dyn_layout(uint32_t kind, uint32_t strategy, uint
 struct SDesc {
     const uint8_t *elements;
     const GLOBAL uint32_t *offsets, *lengths, *pparam;
-    GLOBAL uint32_t *agg_count, *agg_min, *agg_max, *out_items;
-    GLOBAL unsigned long long *agg_sum, *lookback, *stats;
+    GLOBAL uint32_t *agg_count, *agg_min, *agg_max, *agg_kcount, *out_items;
+    GLOBAL unsigned long long *agg_sum, *agg_ksum, *lookback, *stats;
     uint32_t n_parents, n_elements, B, claim_begin;
 };
 __device__ __forceinline__ SDesc load_sdesc(const StreamDev &s) {
@@ -417,6 +425,8 @@ __device__ __forceinline__ SDesc load_sdesc(const StreamDev &s) {
     d.agg_sum = gbl(uni_ptr(s.agg_sum));
     d.agg_min = gbl(uni_ptr(s.agg_min));
     d.agg_max = gbl(uni_ptr(s.agg_max));
+    d.agg_kcount = gbl(uni_ptr(s.agg_kcount));
+    d.agg_ksum = gbl(uni_ptr(s.agg_ksum));
     d.out_items = gbl(uni_ptr(s.out_items));
     d.lookback = gbl(uni_ptr(s.lookback));
     d.stats = gbl(uni_ptr(s.stats));
@@ -456,17 +466,21 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     constexpr bool TAGQ = TAG || HYB;                    // queued items carry their region's tag
     constexpr bool SIGQ = (STRAT == RS_SIGNAL);          // signals cap every downstream ensemble
     constexpr bool PERLANE = WALK || HYB;                // the aggregating node resolves regions per lane
-    constexpr bool HAS_E = (KIND == RS_HASH_EXPAND || KIND == RS_TEXT_WORDS);
+    constexpr bool HASHK = (KIND == RS_HASH_EXPAND || KIND == RS_HASH_TREE);
+    // the tree topology: the filter (the enumerating node) has two children, the expansion and an
+    // aggregating node of its own, which sums the filter's survivors per region
+    constexpr bool TREE = (KIND == RS_HASH_TREE);
+    constexpr bool HAS_E = (HASHK || KIND == RS_TEXT_WORDS);
     constexpr bool BYTES = (KIND == RS_TEXT_WORDS);
     constexpr bool CTXP = (KIND == RS_GRAPH_THRESH);
-    constexpr uint32_t KE = (KIND == RS_HASH_EXPAND) ? 3u : 1u;   // outputs per input of E, at most
+    constexpr uint32_t KE = HASHK ? 3u : 1u;   // outputs per input of E, at most
     using G = Geo<V>;
     constexpr uint32_t EW = G::EW, SQ = G::SQ, R = G::R;
     const uint32_t D1 = a.qdepth;                       // data slots in front of the second node
     const uint32_t D2 = depth2(KIND, EW, D1);           // in front of the third node
     const uint32_t DA = HAS_E ? D2 : D1;                // the aggregating node's input queue
     static_assert(!LANES || (KIND != RS_TEXT_WORDS && V <= 4), "lane-resolved signals: u32 kinds, w <= 256");
-    constexpr bool FUSE = (KIND == RS_HASH_EXPAND);   // fused firings, below
+    constexpr bool FUSE = HASHK;   // fused firings, below
     constexpr uint32_t FL = 3u * EW + 66u, FDUMP = FL;
 
     __shared__ uint32_t fsl[BYTES ? 1 : EW];   // staging slot for the enumerating node's next ensemble
@@ -485,6 +499,8 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     uint32_t *const s_cnt = (uint32_t *)(dyn + lay.cnt);
     uint32_t *const s_min = (uint32_t *)(dyn + lay.mn);
     uint32_t *const s_max = (uint32_t *)(dyn + lay.mx);
+    uint32_t *const s_kcnt = (uint32_t *)(dyn + lay.kcnt);                       // tree: second sink
+    unsigned long long *const s_ksum = (unsigned long long *)(dyn + lay.ksum);
 
     const uint32_t t = threadIdx.x;
     GLOBAL uint32_t *const ctl = gbl(a.ctl);
@@ -691,6 +707,10 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             s_sum[i] = 0ull;
             s_min[i] = 0xFFFFFFFFu;
             s_max[i] = 0;
+            if constexpr (TREE) {
+                s_kcnt[i] = 0;
+                s_ksum[i] = 0ull;
+            }
         }
 
         // The claim's regions must be ordered and inside the element array before any element
@@ -803,7 +823,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 bool kp;
                 if constexpr (KIND == RS_MODFILTER) {
                     kp = mod_pow2 ? ((x & (modm - 1u)) == modr) : (x % modm == modr);
-                } else if constexpr (KIND == RS_HASH_EXPAND) {
+                } else if constexpr (HASHK) {
                     const uint32_t h = fmix32(x ^ salt_key(0));
                     kp = h & 1u;
                     aux = (h >> 1) & 3u;
@@ -849,7 +869,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                         uint32_t item, aux;
                         const uint32_t j = WALK ? reg[k] : fj;
                         const bool keep = f_item(i, i < e, fpos, BYTES ? 0u : x[k], j, thr, ls, lv, item, aux);
-                        const uint32_t nout = keep ? (KIND == RS_HASH_EXPAND ? aux : 1u) : 0u;
+                        const uint32_t nout = keep ? (HASHK ? aux : 1u) : 0u;
                         n_out += (uint32_t)__popcll(__ballot(nout & 1u)) + 2u * (uint32_t)__popcll(__ballot(nout & 2u));
                     }
                     if constexpr (WALK) {
@@ -965,6 +985,33 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 
         if (spos != fpos) stage(fpos);
 
+        // tree: the second sink's per-lane accumulators (the filter's survivors) and their region
+        uint32_t k2c = 0, k2r = 0;
+        unsigned long long k2s = 0;
+        auto flush2 = [&]() {   // per lane, into the region's slots (LDS atomics)
+            if constexpr (TREE) {
+                if (k2c) {
+                    atomicAdd(&s_kcnt[k2r], k2c);
+                    atomicAdd(&s_ksum[k2r], k2s);
+                }
+                k2c = 0;
+                k2s = 0;
+            }
+        };
+        // the second sink takes survivor x of region j (per lane)
+        auto sink2 = [&](bool keep, uint32_t x, uint32_t j) {
+            if constexpr (TREE) {
+                if (keep) {
+                    if (j != k2r) {
+                        flush2();
+                        k2r = j;
+                    }
+                    k2c += 1u;
+                    k2s += (unsigned long long)x;
+                }
+            }
+        };
+
         // per-lane flush of the accumulator into region slot j (LDS atomics)
         auto flush_lane = [&](uint32_t j) {
             if (acc.cnt) {
@@ -1028,7 +1075,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             for (int k = 0; k < V; ++k) {
                 // the expansion's children arrive as pre-images x ^ K(j+1); finishing the hash
                 // here completes H(x, j+1)
-                if constexpr (KIND == RS_HASH_EXPAND) y[k] = fmix32(y[k]);
+                if constexpr (HASHK) y[k] = fmix32(y[k]);
             }
             if (out_items) {
 #pragma unroll
@@ -1142,7 +1189,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             for (int k = 0; k < V; ++k) {
                 const uint32_t pos = (h1 + (uint32_t)k * 64u + t) & (D1 - 1u);
                 x[k] = q1v[pos];
-                if constexpr (KIND == RS_HASH_EXPAND) c[k] = q1a[pos]; else c[k] = 1u;
+                if constexpr (HASHK) c[k] = q1a[pos]; else c[k] = 1u;
                 if constexpr (TAGQ) tg[k] = q1t[pos]; else tg[k] = 0u;
             }
             // output counts of every round (they do not depend on the word lengths below)
@@ -1216,7 +1263,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                         const uint64_t m = FIT ? __ballot(ch < nout) : (__ballot(ch < nout) & fits);
                         const uint32_t pos = pick(m, sl, D2 + t);
                         // child ch of x leaves as its pre-image x ^ K(ch+1) (hash kind); a word as its length
-                        q2v[pos] = KIND == RS_HASH_EXPAND ? x[k] ^ salt_key(ch + 1u) : x[k];
+                        q2v[pos] = HASHK ? x[k] ^ salt_key(ch + 1u) : x[k];
                         if constexpr (TAGQ) q2t[pos] = (uint8_t)tg[k];
                     }
                     run += (uint32_t)__popcll(b0[k]) + 2u * (uint32_t)__popcll(b1[k]);
@@ -1262,7 +1309,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             constexpr bool FULL = decltype(full)::value;
             // the items' own regions: for tags, and for lane-resolved signals of a kind that reads
             // the parent's context
-            constexpr bool FREG = TAG || (LANES && CTXP);
+            constexpr bool FREG = TAG || (LANES && (CTXP || TREE));
             bool one = true;
             if constexpr (FREG) one = jnext > fpos + e - 1u;
             uint32_t reg[V], x[V];
@@ -1289,13 +1336,14 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint32_t i = (uint32_t)k * 64u + t;
                 uint32_t item, aux;
                 const bool keep = f_item(i, FULL || i < e, fpos, x[k], reg[k], thr, ls, lv, item, aux);
+                sink2(keep, x[k], reg[k]);   // the tree's second child of the filter
                 const uint64_t b = __ballot(keep);
                 kb[k] = b;
                 const uint32_t within = rank_below(b), pc = (uint32_t)__popcll(b);
                 // dropped lanes write spill slots on the banks the kept ones leave free
                 const uint32_t pos = pick(b, (t1 + run + within) & (D1 - 1u), D1 + ((t1 + run + pc + t - within) & 63u));
                 q1v[pos] = item;
-                if constexpr (KIND == RS_HASH_EXPAND) q1a[pos] = (uint8_t)aux;
+                if constexpr (HASHK) q1a[pos] = (uint8_t)aux;
                 if constexpr (TAGQ) q1t[pos] = (uint8_t)reg[k];
                 run += pc;
             }
@@ -1430,8 +1478,14 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // off+2, off+1, off in that order; a slot past a lane's last child belongs to a later
         // item of the firing, whose own (later) write of a smaller child index lands on it, or
         // lies past the firing's last child.  Lanes without children write their dump slots.
-        auto fuse_fe = [&](auto counting, const uint32_t *src, uint32_t lt) -> uint32_t {
+        auto fuse_fe = [&](auto counting, const uint32_t *src, uint32_t lt, uint32_t region) -> uint32_t {
             constexpr bool COUNT = decltype(counting)::value;   // E's item count for the statistics
+            if constexpr (TREE) {   // the ensemble's survivors all belong to one region
+                if (k2r != region) {
+                    flush2();
+                    k2r = region;
+                }
+            }
             uint32_t x[V];
 #pragma unroll
             for (int k = 0; k < V; ++k) x[k] = src[k * 64 + (int)t];
@@ -1443,6 +1497,10 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint64_t b0 = __ballot((h & 3u) == 3u);
                 const uint64_t b1 = __ballot((h & 5u) == 5u);
                 if constexpr (COUNT) kept += (uint32_t)__popcll(__ballot(h & 1u));
+                if constexpr (TREE) {   // the tree's second child of the filter
+                    k2c += h & 1u;
+                    k2s += (unsigned long long)((h & 1u) ? x[k] : 0u);
+                }
                 const uint32_t off = run + rank_below(b0) + 2u * rank_below(b1);
                 const uint32_t dst = pick(b0 | b1, off, FDUMP + t);
                 q2v[dst + 2u] = x[k] ^ salt_key(3u);
@@ -1522,7 +1580,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if (ahead) wait_vmem<copy_ops<V>()>(); else wait_vmem<0>();
                 // ---- F and E, then A on every whole round
                 const uint32_t *src = in2 ? q1v : fsl;
-                const uint32_t nt = collect ? fuse_fe(BoolC<true>{}, src, lt) : fuse_fe(BoolC<false>{}, src, lt);
+                const uint32_t reg = WALK ? utag : fj;   // the ensemble's region
+                const uint32_t nt =
+                    collect ? fuse_fe(BoolC<true>{}, src, lt, reg) : fuse_fe(BoolC<false>{}, src, lt, reg);
                 t2 += nt - lt;
                 fpos += EW;
                 const uint32_t used = fuse_a(nt);
@@ -1800,6 +1860,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         }
 
         if constexpr (PERLANE) flush_wave(utag);
+        flush2();
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no staged copy outlives the claim
         order();
         if (failed && t == 0) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1813,6 +1874,10 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if (a.agg_fields & RS_SUM) se.agg_sum[p] = s_sum[i];
                 if (a.agg_fields & RS_MIN) se.agg_min[p] = s_min[i];
                 if (a.agg_fields & RS_MAX) se.agg_max[p] = s_max[i];
+                if constexpr (TREE) {
+                    if (a.agg_fields & RS_KEPT_COUNT) se.agg_kcount[p] = s_kcnt[i];
+                    if (a.agg_fields & RS_KEPT_SUM) se.agg_ksum[p] = s_ksum[i];
+                }
             }
             if (a.collect_stats && t < ST_SIGNALS + 3 && stv)
                 __hip_atomic_fetch_add(&se.stats[t], (unsigned long long)stv, __ATOMIC_RELAXED,
@@ -1880,7 +1945,7 @@ static KernelFn pick_lanes(uint32_t w) {
 // Enumeration with tags downstream (the per-stage choice): kinds with a second stage.
 template <int KIND>
 static KernelFn pick_enum_tag(uint32_t w) {
-    if constexpr (KIND == RS_HASH_EXPAND || KIND == RS_TEXT_WORDS) {
+    if constexpr (KIND == RS_HASH_EXPAND || KIND == RS_HASH_TREE || KIND == RS_TEXT_WORDS) {
         return pick_width<KIND, RS_ENUM_TAG>(w);
     } else {
         return nullptr;
@@ -1904,6 +1969,7 @@ static KernelFn pick(uint32_t kind, uint32_t s, uint32_t w) {
         case RS_HASH_EXPAND: return pick_strategy<RS_HASH_EXPAND>(s, w);
         case RS_TEXT_WORDS: return pick_strategy<RS_TEXT_WORDS>(s, w);
         case RS_GRAPH_THRESH: return pick_strategy<RS_GRAPH_THRESH>(s, w);
+        case RS_HASH_TREE: return pick_strategy<RS_HASH_TREE>(s, w);
         default: return nullptr;
     }
 }
@@ -1934,7 +2000,8 @@ int launch_probe_copy(const void *src, void *dst, unsigned long long bytes, uint
 // ---------------------------------------------------------------- no-allocation scratch
 
 static_assert(CTL_WORDS * 4u == NOALLOC_TABLE_OFF, "control block fills the scratch's first part");
-static_assert(sizeof(StreamDev) <= 128u && sizeof(NoallocTable) <= 4096u, "table fits its part and a kernel argument");
+static_assert(sizeof(StreamDev) <= NOALLOC_TABLE_STRIDE && sizeof(NoallocTable) <= 4096u,
+              "table fits its part and a kernel argument");
 
 // Device state of the no-allocation entry point: control block, stream table, statistics.  Each
 // device holds its own copy until the process ends; calls on one device share it.  Host code

@@ -56,7 +56,9 @@ void clear_error() { g_err[0] = '\0'; }
         if (e_ != hipSuccess) return fail(code, "%s: %s", #expr, hipGetErrorString(e_));     \
     } while (0)
 
-uint32_t k_max_of(uint32_t kind) { return kind == RS_HASH_EXPAND ? 3u : 1u; }
+uint32_t k_max_of(uint32_t kind) { return kind == RS_HASH_EXPAND || kind == RS_HASH_TREE ? 3u : 1u; }
+// aggregate fields a kind stores: the tree adds its second sink's
+uint32_t fields_of(uint32_t kind) { return kind == RS_HASH_TREE ? 63u : 15u; }
 uint32_t elem_bytes_of(uint32_t kind) { return kind == RS_TEXT_WORDS ? 1u : 4u; }
 
 const uint32_t kWidths[] = {64, 128, 256, 512, 1024};
@@ -176,7 +178,7 @@ struct Stream {
     const void *elements = nullptr;
     const uint32_t *offsets = nullptr, *lengths = nullptr, *pparam = nullptr;
     DevBuf own_elements, own_offsets, own_lengths, own_pparam;
-    DevBuf count, sum, min, max, stats;
+    DevBuf count, sum, min, max, kcount, ksum, stats;
     DevBuf out, lookback;          // ordered output stream and its per-claim look-back words
     uint64_t out_cap = 0;
     uint32_t B = 1, n_claims = 0;  // parents per claim and claims, planned at launch
@@ -380,6 +382,8 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
         e.agg_sum = (unsigned long long *)s->sum.p;
         e.agg_min = (uint32_t *)s->min.p;
         e.agg_max = (uint32_t *)s->max.p;
+        e.agg_kcount = (uint32_t *)s->kcount.p;
+        e.agg_ksum = (unsigned long long *)s->ksum.p;
         e.stats = (unsigned long long *)s->stats.p;   // the error word is always written
         if (p->d.emit_outputs && !probe) {
             const size_t lb_bytes = 8ull * s->n_claims + 8;
@@ -638,14 +642,15 @@ RS_API int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out) {
     *out = nullptr;
     if (d->abi_version != RS_ABI_VERSION)
         return fail(RS_EINVAL, "abi_version %u, library is %u", d->abi_version, RS_ABI_VERSION);
-    if (d->kind < RS_MODFILTER || d->kind > RS_GRAPH_THRESH) return fail(RS_EINVAL, "unknown kind %u", d->kind);
+    if (d->kind < RS_MODFILTER || d->kind > RS_HASH_TREE) return fail(RS_EINVAL, "unknown kind %u", d->kind);
     if (d->strategy > RS_ENUM_TAG) return fail(RS_EINVAL, "unknown strategy %u", d->strategy);
     if (d->strategy == RS_ENUM_TAG && !rs::kernel_supported(d->kind, RS_ENUM_TAG, d->ensemble_width ? d->ensemble_width : 64))
         return fail(RS_EINVAL, "enumeration with tags downstream is offered for kinds with a second stage");
     if (d->strategy == RS_SIGNAL_LANES && !rs::kernel_supported(d->kind, RS_SIGNAL_LANES, d->ensemble_width ? d->ensemble_width : 64))
         return fail(RS_EINVAL, "lane-resolved signals are offered for u32 kinds only");
-    if (d->agg_fields == 0 || (d->agg_fields & ~15u))
-        return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX");
+    if (d->agg_fields == 0 || (d->agg_fields & ~fields_of(d->kind)))
+        return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX "
+                               "(and RS_KEPT_COUNT|RS_KEPT_SUM for RS_HASH_TREE)");
     const uint32_t w = d->ensemble_width;
     if (w && !rs::kernel_supported(d->kind, RS_TAG, w))
         return fail(RS_EINVAL, "ensemble_width %u not supported (64, 128, 256, 512 or 1024)", w);
@@ -745,7 +750,8 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
 
     // device footprint (look-back words at one per parent at most)
     const uint64_t agg_bytes = P * ((p->d.agg_fields & RS_COUNT ? 4 : 0) + (p->d.agg_fields & RS_SUM ? 8 : 0) +
-                                    (p->d.agg_fields & RS_MIN ? 4 : 0) + (p->d.agg_fields & RS_MAX ? 4 : 0));
+                                    (p->d.agg_fields & RS_MIN ? 4 : 0) + (p->d.agg_fields & RS_MAX ? 4 : 0) +
+                                    (p->d.agg_fields & RS_KEPT_COUNT ? 4 : 0) + (p->d.agg_fields & RS_KEPT_SUM ? 8 : 0));
     uint64_t in_bytes = 0;
     if (s->mem == RS_MEM_HOST)
         in_bytes = s->n_elements * eb + (lens ? 8 * P : 4 * (P + 1)) + (s->parent_param ? 4 * P : 0);
@@ -792,6 +798,8 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
     if (p->d.agg_fields & RS_SUM && (rc = st->sum.alloc(8 * P))) return rc;
     if (p->d.agg_fields & RS_MIN && (rc = st->min.alloc(4 * P))) return rc;
     if (p->d.agg_fields & RS_MAX && (rc = st->max.alloc(4 * P))) return rc;
+    if (p->d.agg_fields & RS_KEPT_COUNT && (rc = st->kcount.alloc(4 * P))) return rc;
+    if (p->d.agg_fields & RS_KEPT_SUM && (rc = st->ksum.alloc(8 * P))) return rc;
     if ((rc = st->stats.alloc(8 * rs::ST_WORDS))) return rc;
     HIP_OR(hipMemsetAsync(st->stats.p, 0, 8 * rs::ST_WORDS, hs), RS_EDEVICE);
     // the copies and the clear have landed before any launch reads them, and the caller may
@@ -908,10 +916,12 @@ RS_API int read_aggregates(rs_pipeline *p, uint64_t stream_id, rs_agg_view *out,
         uint32_t bit;
         const char *name;
     };
-    F fields[4] = {{out->count, &s->count, 4 * P, RS_COUNT, "count"},
+    F fields[6] = {{out->count, &s->count, 4 * P, RS_COUNT, "count"},
                    {out->sum, &s->sum, 8 * P, RS_SUM, "sum"},
                    {out->min, &s->min, 4 * P, RS_MIN, "min"},
-                   {out->max, &s->max, 4 * P, RS_MAX, "max"}};
+                   {out->max, &s->max, 4 * P, RS_MAX, "max"},
+                   {out->kept_count, &s->kcount, 4 * P, RS_KEPT_COUNT, "kept_count"},
+                   {out->kept_sum, &s->ksum, 8 * P, RS_KEPT_SUM, "kept_sum"}};
     for (auto &f : fields) {
         if (!f.dst) continue;
         if (!(p->d.agg_fields & f.bit)) return fail(RS_EINVAL, "field %s is not stored by this pipeline", f.name);
@@ -1123,12 +1133,13 @@ RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams,
     if (n_streams == 0 || n_streams > rs::NOALLOC_MAX_STREAMS)
         return fail(RS_EINVAL, "run_noalloc takes 1 to %u streams per call (got %u)", rs::NOALLOC_MAX_STREAMS, n_streams);
     if (d->abi_version != RS_ABI_VERSION) return fail(RS_EINVAL, "abi_version %u, library is %u", d->abi_version, RS_ABI_VERSION);
-    if (d->kind < RS_MODFILTER || d->kind > RS_GRAPH_THRESH) return fail(RS_EINVAL, "unknown kind %u", d->kind);
+    if (d->kind < RS_MODFILTER || d->kind > RS_HASH_TREE) return fail(RS_EINVAL, "unknown kind %u", d->kind);
     if (d->strategy == RS_AUTO || !rs::kernel_supported(d->kind, d->strategy, d->ensemble_width))
         return fail(RS_EINVAL, "run_noalloc needs an explicit strategy and ensemble width the kernels offer "
                                "(autotuning allocates)");
-    if (d->agg_fields == 0 || (d->agg_fields & ~15u))
-        return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX");
+    if (d->agg_fields == 0 || (d->agg_fields & ~fields_of(d->kind)))
+        return fail(RS_EINVAL, "agg_fields must be a non-empty OR of RS_COUNT|RS_SUM|RS_MIN|RS_MAX "
+                               "(and RS_KEPT_COUNT|RS_KEPT_SUM for RS_HASH_TREE)");
     if (d->emit_outputs) return fail(RS_EINVAL, "run_noalloc does not produce the ordered output stream");
     const uint32_t qdepth = d->queue_depth ? d->queue_depth : 2 * d->ensemble_width;
     if (!depth_ok(d->ensemble_width, qdepth))
@@ -1139,6 +1150,7 @@ RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams,
     const uint32_t eb = elem_bytes_of(d->kind);
     rs::NoallocTable tab;
     std::memset(&tab, 0, sizeof tab);
+    static_assert(sizeof(rs::StreamDev) <= rs::NOALLOC_TABLE_STRIDE, "stream table entry");
     tab.n = n_streams;
     uint64_t claims = 0;
     uint32_t bmax = 1;
@@ -1157,7 +1169,9 @@ RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams,
         if ((uintptr_t)s.elements & 15u) return fail(RS_EINVAL, "stream %u: element array must be 16-byte aligned", i);
         const rs_agg_view &o = out[i];
         if (s.n_parents && (((d->agg_fields & RS_COUNT) && !o.count) || ((d->agg_fields & RS_SUM) && !o.sum) ||
-                            ((d->agg_fields & RS_MIN) && !o.min) || ((d->agg_fields & RS_MAX) && !o.max)))
+                            ((d->agg_fields & RS_MIN) && !o.min) || ((d->agg_fields & RS_MAX) && !o.max) ||
+                            ((d->agg_fields & RS_KEPT_COUNT) && !o.kept_count) ||
+                            ((d->agg_fields & RS_KEPT_SUM) && !o.kept_sum)))
             return fail(RS_EINVAL, "stream %u: a destination of a requested field is NULL", i);
         uint32_t B = 1, nc = 0;
         const uint32_t P = (uint32_t)s.n_parents;
@@ -1171,6 +1185,8 @@ RS_API int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams,
         e.agg_sum = (unsigned long long *)o.sum;
         e.agg_min = o.min;
         e.agg_max = o.max;
+        e.agg_kcount = o.kept_count;
+        e.agg_ksum = (unsigned long long *)o.kept_sum;
         e.n_parents = P;
         e.n_elements = (uint32_t)s.n_elements;
         e.parents_per_claim = B;

@@ -55,7 +55,8 @@ def _desc(**kw):
 @pytest.mark.parametrize("bad", [
     dict(abi_version=99), dict(kind=0), dict(kind=9), dict(strategy=7), dict(agg_fields=0),
     dict(agg_fields=16), dict(ensemble_width=100), dict(ensemble_width=2048), dict(queue_depth=300),
-    dict(queue_depth=256), dict(queue_depth=4096), dict(emit_outputs=2),
+    dict(queue_depth=256), dict(queue_depth=4096), dict(emit_outputs=2), dict(agg_fields=16),
+    dict(kind=6), dict(kind=5, agg_fields=64),
 ])
 def test_bad_descriptions_are_rejected_on_the_host(bad):
     h = ctypes.c_void_p()

@@ -176,3 +176,16 @@ def test_serving_512_streams_one_batch():
             o, v = streams[s]
             ref = oracle.run(oracle.HASH_EXPAND, o, v)
             check(p.read(ids[s]), ref, ("count", "sum", "min", "max"), f"stream {s}")
+
+
+@pytest.mark.parametrize("L", [16, 4096])
+def test_tree_2p26(L):
+    """The tree topology at the headline size, widths from the autotuner."""
+    n = 1 << 26
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_TREE, offsets, vals)
+    for s in ALL3 + [rs.RS_ENUM_TAG]:
+        say("2^26 tree L", L, s)
+        got, _ = run_dev(rs.RS_HASH_TREE, s, offsets, vals, fields=rs.DEFAULT_FIELDS[rs.RS_HASH_TREE])
+        check(got, ref, ("count", "sum", "min", "max", "kept_count", "kept_sum"), f"2^26 tree L={L} {s}")

@@ -722,3 +722,75 @@ def test_taxi_shape_three_versions(width):
         full[s] = [st.full[k] / max(1, st.firings[k]) for k in range(3)]
     assert full[rs.RS_SIGNAL][0] > 0.5 and full[rs.RS_ENUM_TAG][0] > 0.5     # stage 1: long regions
     assert full[rs.RS_ENUM_TAG][1] > full[rs.RS_SIGNAL][1]                  # stage 2: tags fill ensembles
+
+
+# ---- tree topology: the filter feeds the expansion and a second sink (RS_HASH_TREE) ----
+
+TREE_FIELDS = ("count", "sum", "min", "max", "kept_count", "kept_sum")
+TREE_STRATS = ALL3 + [rs.RS_ENUM_TAG]
+
+
+@pytest.mark.parametrize("L", [1, 5, 16, 64, 256, 1000, 4096])
+@pytest.mark.parametrize("strategy", TREE_STRATS)
+def test_tree_fixed_L(L, strategy):
+    n = (1 << 18) + 13
+    say("tree L", L, SNAME[strategy])
+    offsets = workloads.fixed_offsets(n, L)
+    vals = workloads.hash_values(2, n)
+    ref = oracle.run(oracle.HASH_TREE, offsets, vals)
+    got, _ = run_one(rs.RS_HASH_TREE, strategy, 256, offsets, vals, fields=rs.DEFAULT_FIELDS[rs.RS_HASH_TREE])
+    check(got, ref, TREE_FIELDS, f"tree L={L} {SNAME[strategy]}")
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+@pytest.mark.parametrize("strategy", TREE_STRATS)
+def test_tree_widths_variable_regions(width, strategy):
+    skip_unoffered(rs.RS_HASH_TREE, strategy, width)
+    say("tree width", width, SNAME[strategy])
+    offsets = workloads.uniform_offsets(5, 3000, 300)
+    vals = workloads.hash_values(5, int(offsets[-1]))
+    ref = oracle.run(oracle.HASH_TREE, offsets, vals)
+    got, _ = run_one(rs.RS_HASH_TREE, strategy, width, offsets, vals, fields=rs.DEFAULT_FIELDS[rs.RS_HASH_TREE],
+                     device=True)
+    check(got, ref, TREE_FIELDS, f"tree width {width} {SNAME[strategy]}")
+
+
+@pytest.mark.parametrize("strategy", TREE_STRATS)
+def test_tree_edge_cases_and_second_sink_alone(strategy):
+    say("tree edge cases", SNAME[strategy])
+    offs = np.zeros(1001, np.uint32)
+    got, _ = run_one(rs.RS_HASH_TREE, strategy, 256, offs, np.zeros(4, np.uint32),
+                     fields=rs.DEFAULT_FIELDS[rs.RS_HASH_TREE])
+    assert (got["kept_count"] == 0).all() and (got["kept_sum"] == 0).all() and (got["count"] == 0).all()
+    vals = workloads.hash_values(4, 5000)
+    offs = np.array([7, 7, 100, 2500, 4990], np.uint32)
+    ref = oracle.run(oracle.HASH_TREE, offs, vals)
+    got, _ = run_one(rs.RS_HASH_TREE, strategy, 128, offs, vals, fields=rs.DEFAULT_FIELDS[rs.RS_HASH_TREE])
+    check(got, ref, TREE_FIELDS, "tree offset start")
+    # the second sink alone
+    got, _ = run_one(rs.RS_HASH_TREE, strategy, 64, offs, vals, fields=rs.RS_KEPT_COUNT | rs.RS_KEPT_SUM)
+    check(got, ref, ("kept_count", "kept_sum"), "tree second sink alone")
+
+
+@pytest.mark.parametrize("strategy", TREE_STRATS)
+def test_tree_output_stream_and_batch(strategy):
+    """The first sink's ordered output stream equals the linear pipeline's; a batch of streams of
+    very different region lengths gives each stream's own records."""
+    say("tree outputs and batch", SNAME[strategy])
+    n = 150001
+    offsets = workloads.fixed_offsets(n, 37)
+    vals = workloads.hash_values(9, n)
+    ref = oracle.run(oracle.HASH_TREE, offsets, vals, emit_outputs=True)
+    with rs.Pipeline(rs.RS_HASH_TREE, strategy=strategy, ensemble_width=256, emit_outputs=True) as p:
+        sid = p.push(offsets, vals)
+        p.run()
+        got, out = p.read(sid), p.outputs(sid)
+    check(got, ref, TREE_FIELDS, "tree outputs agg")
+    assert np.array_equal(out, ref.out)
+    shapes = [(5000, 1.0), (60000, 37.5), (100000, 700.0), (7, 3.0)]
+    ins = [workloads.serving_stream(51, i, nn, m) for i, (nn, m) in enumerate(shapes)]
+    with rs.Pipeline(rs.RS_HASH_TREE, strategy=strategy, ensemble_width=128) as p:
+        ids = [p.push(o, v) for o, v in ins]
+        p.run()
+        for i, (o, v) in zip(ids, ins):
+            check(p.read(i), oracle.run(oracle.HASH_TREE, o, v), TREE_FIELDS, "tree batch")
