@@ -196,25 +196,33 @@ typedef struct {
     uint64_t n_outputs;
 } rs_stats_t;
 
-/* Validate the description and create a pipeline.  Allocates the pipeline's control block
- * on the current HIP device and a HIP stream of default priority.
+/* Validate the description and create a pipeline: the application of §2.1, nodes joined by
+ * fixed-size data queues, whose first node enumerates each parent into its elements (§4) and
+ * whose last aggregates each region (§4.1), every node firing ensembles of at most w items
+ * (§2.2).  Creates the pipeline's HIP streams (default priority) on the current device; device
+ * memory is taken at stream_push and run.  *out is library-owned until pipeline_destroy.
  * Errors: RS_EINVAL (bad description), RS_ENOMEM, RS_EDEVICE. */
 int pipeline_create(const rs_pipeline_desc *d, rs_pipeline **out);
 
 /* Make the pipeline enqueue its work on the given HIP stream (hipStream_t) instead of its own;
- * NULL restores the pipeline's own stream.  Errors: RS_EINVAL. */
+ * NULL restores the pipeline's own stream.  Host plumbing, no passage of the paper.
+ * Errors: RS_EINVAL. */
 int pipeline_set_stream(rs_pipeline *p, void *hip_stream);
 
-/* Register one input stream.  Validates it (host memory: offsets monotone and in range, in
- * O(P)), copies host arrays to the device, allocates the aggregate arrays and returns an id.
+/* Register one input stream: a sequence of parents, each with its element count or range (the
+ * findCount of §4; the text application of §5 is given line start indices and lengths) and an
+ * optional per-parent context (getParent, §4.1).  Validates it (host memory: offsets monotone
+ * and in range, in O(P)), copies host arrays to the device, allocates the aggregate arrays and
+ * returns an id.
  * Errors: RS_EINVAL (malformed stream, with a message), RS_EBUDGET (larger than the whole
  * budget), RS_ENOMEM, RS_EDEVICE. */
 int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id);
 
 /* Process every pushed stream that has not run yet: admitted streams (by budget) go into one
  * persistent launch in which one-wave processors take parent batches from per-XCD
- * partitions of the launch's claims, by index or from a partition counter (§2.2);
- * streams that do not fit wait for the next run().  RS_RUN_SYNC waits for completion.
+ * partitions of the launch's claims, by index or from a partition counter, and the kernel
+ * returns only when every claim is consumed (§2.2); streams that do not fit wait for the next
+ * run().  RS_RUN_SYNC waits for completion.
  * Errors: RS_EDEVICE (HIP error or watchdog), RS_ESTATE (nothing to run is not an error: RS_OK). */
 int run(rs_pipeline *p, uint32_t flags);
 
@@ -224,18 +232,21 @@ int run(rs_pipeline *p, uint32_t flags);
  * Errors: RS_ESTATE (no batch has run), RS_EDEVICE. */
 int run_again(rs_pipeline *p, uint32_t flags);
 
-/* Copy one stream's per-parent aggregates into caller-owned arrays (host memory, or device
- * memory with RS_READ_DEVICE).  Waits for the stream's run unless RS_NONBLOCK.
+/* Copy one stream's per-parent aggregates, the record end() emits for each region (§4.1,
+ * begin/run/end bracket every parent, empty ones included), into caller-owned arrays (host
+ * memory, or device memory with RS_READ_DEVICE).  Waits for the stream's run unless RS_NONBLOCK.
  * Errors: RS_ENOTFOUND, RS_ESTATE (stream never ran), RS_ENOTREADY, RS_EDEVICE. */
 int read_aggregates(rs_pipeline *p, uint64_t stream_id, rs_agg_view *out, uint32_t flags);
 
-/* Copy the ordered output stream (serial order: parent, element index, child index) of a
- * pipeline created with emit_outputs = 1.  *n_out receives the full length; at most cap items
+/* Copy the ordered output stream, the survivors stripped of their parent context (§4), in serial
+ * order (parent, element index, child index), of a pipeline created with emit_outputs = 1.  *n_out receives the full length; at most cap items
  * are written.  Errors as read_aggregates, plus RS_EINVAL when emit_outputs was 0. */
 int read_outputs(rs_pipeline *p, uint64_t stream_id, uint32_t *out, uint64_t cap,
                  uint64_t *n_out, uint32_t flags);
 
-/* Device statistics of one stream (zeros unless RS_COLLECT_STATS).  Errors as read_aggregates. */
+/* Device statistics of one stream (zeros unless RS_COLLECT_STATS): firings, items and full
+ * ensembles per node, the occupancy measure of §5 (full ensembles 91% vs 9% of firings).
+ * Errors as read_aggregates. */
 int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out);
 
 /* Measurement aid (pipelines created with RS_TIME_KERNEL): the device time of the pipeline
@@ -247,8 +258,8 @@ int rs_stats(rs_pipeline *p, uint64_t stream_id, rs_stats_t *out);
  * Errors: RS_EINVAL (NULL p or n, or the pipeline lacks RS_TIME_KERNEL), RS_EDEVICE. */
 int kernel_times(rs_pipeline *p, float *ms, uint32_t cap, uint32_t *n);
 
-/* Free a finished stream's device state; its id becomes unknown.  Errors: RS_ENOTFOUND,
- * RS_ESTATE (still running). */
+/* Free a finished stream's device state; its id becomes unknown.  Host plumbing, no passage of
+ * the paper.  Errors: RS_ENOTFOUND, RS_ESTATE (still running). */
 int stream_release(rs_pipeline *p, uint64_t stream_id);
 
 /* One request of the serving loop: its input stream and when it arrives, in seconds after
@@ -270,7 +281,8 @@ typedef struct {
     uint32_t pad;
 } rs_request_timing;
 
-/* Serve a sequence of requests in real time (continuous batching).  The loop pushes every
+/* Serve a sequence of requests in real time (continuous batching, beyond the paper, whose
+ * kernel consumes one input stream per launch, §2.2).  The loop pushes every
  * request whose arrival time has passed, admits pushed requests into a new batch whenever
  * one of the pipeline's two launch lanes is free and the HBM budget allows (requests that
  * do not fit wait for earlier ones to finish and release their memory), reaps finished
@@ -312,10 +324,11 @@ int run_noalloc(const rs_pipeline_desc *d, const rs_stream_desc *streams, uint32
 int hbm_probe(const void *src, void *dst, uint64_t bytes, void *hip_stream);
 
 /* Wait for outstanding work and free everything the pipeline owns.  Borrowed memory is
- * untouched. */
+ * untouched.  Host plumbing, no passage of the paper. */
 int pipeline_destroy(rs_pipeline *p);
 
-/* Message of the last failure on this thread ("" if none). */
+/* Message of the last failure on this thread ("" if none; a thread-local buffer the library
+ * owns, valid until the thread's next call). */
 const char *rs_last_error(void);
 
 #ifdef __cplusplus
