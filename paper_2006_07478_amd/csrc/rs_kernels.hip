@@ -205,6 +205,13 @@ __device__ __forceinline__ void wait_vmem() {
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
+// Bit 7 of each byte of the result is set where that byte of w is a space (0x20), exactly: the
+// sum inside never carries from one byte into the next.
+__device__ __forceinline__ uint32_t space_bytes(uint32_t w) {
+    const uint32_t z = w ^ 0x20202020u;
+    return ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;
+}
+
 template <bool B>
 struct BoolC {
     static constexpr bool value = B;
@@ -483,7 +490,10 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     constexpr bool FUSE = HASHK;   // fused firings, below
     constexpr uint32_t FL = 3u * EW + 66u, FDUMP = FL;
 
-    __shared__ uint32_t fsl[BYTES ? 1 : EW];   // staging slot for the enumerating node's next ensemble
+    // text: a firing's bytes from the word before its first address, in 1, 1, 2, 4 or 8 copies of
+    // 256 bytes (at least w + 8 bytes)
+    constexpr uint32_t TB = V <= 2 ? 256u : 2u * EW;
+    __shared__ uint32_t fsl[BYTES ? TB / 4u : EW];   // staging slot for the enumerating node's next ensemble
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
 
     const Dyn lay = dyn_layout(KIND, STRAT, EW, D1, a.bmax);
@@ -763,6 +773,19 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
             }
         };
+        // text: the window of bytes [tsbase, tsbase + TB) holding the firing at address tspos, from
+        // the word before it (for the byte before the first); bytes past the array read as zero
+        uint32_t tspos = 0xFFFFFFFFu, tsbase = 0;
+        auto stage_text = [&](uint32_t adr) {
+            if constexpr (BYTES) {
+                const uint32_t base = adr >= 4u ? (adr & ~3u) - 4u : 0u;
+                tspos = adr;
+                tsbase = base;
+                if (base < sd.n_elements)
+                    lds_copy<TB / 256u>(rsrc_words(elems + base, min(TB, sd.n_elements - base)), uni(lds_addr(fsl)), t,
+                                        false);
+            }
+        };
         // u32 elements outside the staged path (the output-count pass): plain buffer loads
         auto load_ens = [&](uint32_t pos, uint32_t n, uint32_t (&x)[V]) {
             const __amdgpu_buffer_rsrc_t r = rsrc(elems + (size_t)pos * 4u, n * 4u);
@@ -815,8 +838,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // The first stage on item i = k*64 + lane of an ensemble at fpos_: whether it passes,
         // the value it carries on, and the hash kind's child count.  x is the element (u32
         // kinds); j the item's region, ls_/lv_ its line's address and position (text).
-        auto f_item = [&](uint32_t i, bool act, uint32_t fpos_, uint32_t x, uint32_t j, uint32_t thr, uint32_t ls_,
-                          uint32_t lv_, uint32_t &item, uint32_t &aux) -> bool {
+        // text: bytes from the staging window (staged) or by buffer loads (the output-count pass)
+        auto f_item = [&](auto staged, uint32_t i, bool act, uint32_t fpos_, uint32_t x, uint32_t j, uint32_t thr,
+                          uint32_t ls_, uint32_t lv_, uint32_t &item, uint32_t &aux) -> bool {
             aux = 0;
             if constexpr (!BYTES) {
                 item = x;
@@ -838,8 +862,16 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 item = adr;
                 const bool in_line = act && (!TAG || adr < ls + (VT[j + 1] - VT[j]));
                 const bool at_start = adr == ls;
-                const uint32_t cb = __builtin_amdgcn_raw_buffer_load_b8(rtext, in_line ? adr : 0u, 0, 0);
-                const uint32_t pb = __builtin_amdgcn_raw_buffer_load_b8(rtext, adr - (at_start ? 0u : 1u), 0, 0);
+                uint32_t cb, pb;
+                if constexpr (decltype(staged)::value) {
+                    const uint8_t *tw = (const uint8_t *)fsl;
+                    const uint32_t ix = in_line ? adr - tsbase : 0u;
+                    cb = tw[ix];
+                    pb = tw[ix ? ix - 1u : 0u];
+                } else {
+                    cb = __builtin_amdgcn_raw_buffer_load_b8(rtext, in_line ? adr : 0u, 0, 0);
+                    pb = __builtin_amdgcn_raw_buffer_load_b8(rtext, adr - (at_start ? 0u : 1u), 0, 0);
+                }
                 const uint32_t prev = at_start ? 32u : pb;
                 return in_line && cb != 32u && prev == 32u;
             }
@@ -868,7 +900,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                         const uint32_t i = (uint32_t)k * 64u + t;
                         uint32_t item, aux;
                         const uint32_t j = WALK ? reg[k] : fj;
-                        const bool keep = f_item(i, i < e, fpos, BYTES ? 0u : x[k], j, thr, ls, lv, item, aux);
+                        const bool keep = f_item(BoolC<false>{}, i, i < e, fpos, BYTES ? 0u : x[k], j, thr, ls, lv, item, aux);
                         const uint32_t nout = keep ? (HASHK ? aux : 1u) : 0u;
                         n_out += (uint32_t)__popcll(__ballot(nout & 1u)) + 2u * (uint32_t)__popcll(__ballot(nout & 2u));
                     }
@@ -1204,34 +1236,52 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 total += (uint32_t)__popcll(b0[k]) + 2u * (uint32_t)__popcll(b1[k]);
             }
             if constexpr (BYTES) {
-                // word length: run of non-space bytes from the word's start, within its line,
-                // four bytes at a time
+                // word length: the run of non-space bytes from the word's start, within its line.
+                // Every round's first window (the 16 bytes from the aligned word holding the start)
+                // is requested before any round is examined, so their round trips overlap; a word
+                // that reaches past its window goes on 32 bytes at a time.  Loads are range-checked
+                // word by word (bytes past the array read as zero, which is not a space, and the
+                // line's end bounds the run anyway).
+                uint32_t wv[V][4];
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const bool act = FULL || (uint32_t)k * 64u + t < e;
+                    const uint32_t q = act ? (x[k] & ~3u) : 0u;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) wv[k][d] = __builtin_amdgcn_raw_buffer_load_b32(rtext, q + 4u * d, 0, 0);
+                }
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
                     if (!(FULL || (uint32_t)k * 64u + t < e)) continue;
                     const uint32_t j = TAGQ ? tg[k] : ej;
                     const uint32_t le = SX[j] + (VT[j + 1] - VT[j]);
-                    uint32_t p = x[k];
-                    while (p < le) {
-                        const uint32_t q = p & ~3u;
-                        uint32_t word = 0;
-                        if (q + 8u <= sd.n_elements) {
-                            const uint32_t w0 = __builtin_amdgcn_raw_buffer_load_b32(rtext, q, 0, 0);
-                            const uint32_t w1 = __builtin_amdgcn_raw_buffer_load_b32(rtext, q + 4u, 0, 0);
-                            word = __builtin_amdgcn_alignbyte(w1, w0, p & 3u);
-                        } else {
-                            for (uint32_t b = 0; b < 4u && p + b < le; ++b)
-                                word |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rtext, p + b, 0, 0) << (8u * b);
-                        }
-                        // first space among the four bytes: lowest zero byte of word ^ "    "
-                        const uint32_t z = word ^ 0x20202020u;
-                        const uint32_t zm = (z - 0x01010101u) & ~z & 0x80808080u;
-                        uint32_t step = zm ? ((uint32_t)__builtin_ctz(zm) >> 3) : 4u;
-                        if (le - p < step) step = le - p;
-                        p += step;
-                        if (step < 4u) break;
+                    const uint32_t p = x[k];
+                    const uint32_t a = p & 3u;
+                    uint64_t lo = (uint64_t)space_bytes(wv[k][0]) | ((uint64_t)space_bytes(wv[k][1]) << 32);
+                    uint64_t hi = (uint64_t)space_bytes(wv[k][2]) | ((uint64_t)space_bytes(wv[k][3]) << 32);
+                    if (a) {   // drop the bytes before the start
+                        lo = (lo >> (8u * a)) | (hi << (64u - 8u * a));
+                        hi >>= 8u * a;
                     }
-                    x[k] = p - x[k];
+                    const uint32_t win = 16u - a;   // bytes of the window from the start
+                    uint32_t len = lo ? ((uint32_t)__builtin_ctzll(lo) >> 3) : hi ? 8u + ((uint32_t)__builtin_ctzll(hi) >> 3) : win;
+                    if (len == win && le - p > win) {
+                        // the word reaches past the window
+                        uint32_t q = p + win;   // aligned
+                        for (;;) {
+                            uint32_t m[8];
+#pragma unroll
+                            for (int d = 0; d < 8; ++d) m[d] = space_bytes(__builtin_amdgcn_raw_buffer_load_b32(rtext, q + 4u * d, 0, 0));
+                            uint32_t step = 32u;
+#pragma unroll
+                            for (int d = 7; d >= 0; --d)
+                                if (m[d]) step = 4u * (uint32_t)d + ((uint32_t)__builtin_ctz(m[d]) >> 3);
+                            len += step;
+                            q += 32u;
+                            if (step < 32u || p + len >= le) break;
+                        }
+                    }
+                    x[k] = min(len, le - p);
                 }
             }
             // The firing takes the longest prefix of the ensemble whose outputs fit the free
@@ -1326,6 +1376,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = fsl[k * 64 + t];
             } else {
+                const uint32_t adr0 = TAG ? fpos : ls + (fpos - lv);   // the firing's first byte
+                if (tspos != adr0) stage_text(adr0);
+                wait_vmem<0>();   // the window has landed
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = 0;
             }
@@ -1335,7 +1388,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             for (int k = 0; k < V; ++k) {
                 const uint32_t i = (uint32_t)k * 64u + t;
                 uint32_t item, aux;
-                const bool keep = f_item(i, FULL || i < e, fpos, x[k], reg[k], thr, ls, lv, item, aux);
+                const bool keep = f_item(BoolC<true>{}, i, FULL || i < e, fpos, x[k], reg[k], thr, ls, lv, item, aux);
                 sink2(keep, x[k], reg[k]);   // the tree's second child of the filter
                 const uint64_t b = __ballot(keep);
                 kb[k] = b;
@@ -1370,7 +1423,21 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                     stat(ST_SIGNALS + 0, nbound);
                 }
             }
-            if constexpr (!BYTES) stage(fpos + e);   // the slot's contents are in registers
+            if constexpr (!BYTES) {
+                stage(fpos + e);   // the slot's contents are in registers
+            } else {
+                // the next firing's window: the rest of this line, else the next line (tags: the next
+                // address); a wrong guess is staged again when that firing starts
+                const uint32_t nf = fpos + e;
+                uint32_t nadr = 0xFFFFFFFFu;
+                if constexpr (TAG) {
+                    if (nf < vend) nadr = nf;
+                } else {
+                    if (nf < rend) nadr = ls + (nf - lv);
+                    else if (fj + 1u < nb) nadr = uni(SX[fj + 1u]);
+                }
+                if (nadr != 0xFFFFFFFFu) stage_text(nadr);
+            }
             t1 += run;
             fpos += e;
             stat(ST_FIRINGS + 0, 1u);
