@@ -184,10 +184,15 @@ struct Stream {
     uint32_t B = 1, n_claims = 0;  // parents per claim and claims, planned at launch
     uint64_t footprint = 0;
     uint64_t batch = 0;            // batch this stream runs in
+    hipEvent_t ready = nullptr;    // its host-to-device copies have landed (pushes that do not wait)
+    ~Stream() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
 struct Batch {
     std::vector<uint64_t> ids;
+    std::vector<rs::StreamDev> host_table;   // source of the table's copy, kept until the batch is freed
     DevBuf table, ctl;
     uint32_t total_claims = 0;
     uint32_t grid = 0;
@@ -361,7 +366,8 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     b->width = p->width;
     b->qdepth = p->qdepth;
     b->lane = lane_of(p, batch_id);
-    std::vector<rs::StreamDev> h(sel.size());
+    std::vector<rs::StreamDev> &h = b->host_table;
+    h.resize(sel.size());
     uint64_t claims = 0;
     uint32_t bmax = 1;
     for (size_t i = 0; i < sel.size(); ++i) {
@@ -411,7 +417,9 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     HIP_OR(hipMemsetAsync(b->ctl.p, 0, rs::CTL_WORDS * sizeof(uint32_t), b->lane), RS_EDEVICE);
     HIP_OR(hipMemcpyAsync(b->table.p, h.data(), sizeof(rs::StreamDev) * h.size(), hipMemcpyHostToDevice, b->lane),
            RS_EDEVICE);
-    HIP_OR(hipStreamSynchronize(b->lane), RS_EDEVICE);   // h is a local array
+    // the launch waits on the device, not the host, for streams whose copies are still landing
+    for (Stream *s : sel)
+        if (s->ready) HIP_OR(hipStreamWaitEvent(b->lane, s->ready, 0), RS_EDEVICE);
     HIP_OR(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), RS_EDEVICE);
     b->total_claims = (uint32_t)claims;
     const int per_cu = rs::blocks_per_cu(p->d.kind, p->strategy, p->width, p->qdepth, bmax);
@@ -699,7 +707,18 @@ RS_API int pipeline_set_stream(rs_pipeline *p, void *hip_stream) {
     return RS_OK;
 }
 
+namespace {
+int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bool wait);
+}
+
 RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id) {
+    return push_stream(p, s, stream_id, true);
+}
+
+namespace {
+// wait: return after the copies have landed, so the caller may reuse its host arrays; else the
+// stream's launch waits for them on the device (serve(), whose requests outlive the loop)
+int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bool wait) {
     clear_error();
     if (!p || !stream_id) return fail(RS_EINVAL, "NULL argument");
     int rc = check_stream(p, s);
@@ -802,9 +821,14 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
     if (p->d.agg_fields & RS_KEPT_SUM && (rc = st->ksum.alloc(8 * P))) return rc;
     if ((rc = st->stats.alloc(8 * rs::ST_WORDS))) return rc;
     HIP_OR(hipMemsetAsync(st->stats.p, 0, 8 * rs::ST_WORDS, hs), RS_EDEVICE);
-    // the copies and the clear have landed before any launch reads them, and the caller may
-    // reuse its host arrays as soon as this returns
-    HIP_OR(hipStreamSynchronize(hs), RS_EDEVICE);
+    if (wait) {
+        // the copies and the clear have landed before any launch reads them, and the caller may
+        // reuse its host arrays as soon as this returns
+        HIP_OR(hipStreamSynchronize(hs), RS_EDEVICE);
+    } else {
+        HIP_OR(hipEventCreateWithFlags(&st->ready, hipEventDisableTiming), RS_EDEVICE);
+        HIP_OR(hipEventRecord(st->ready, hs), RS_EDEVICE);
+    }
     if (p->d.emit_outputs && (rc = st->out.alloc(4 * st->out_cap + 16))) return rc;
 
     st->id = p->next_id++;
@@ -812,6 +836,7 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
     p->streams[st->id] = std::move(st);
     return RS_OK;
 }
+}  // namespace
 
 namespace {
 
@@ -1044,7 +1069,7 @@ RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view
         //    completions are not held up behind a long run of copies
         for (int pushed = 0; pushed < 4 && next < n && reqs[next].arrival_s <= now(); ++pushed) {
             uint64_t id = 0;
-            const int rc = stream_push(p, &reqs[next].stream, &id);
+            const int rc = push_stream(p, &reqs[next].stream, &id, false);   // the launch waits for the copy
             if (rc) {
                 fail_req(next, rc);
             } else {
