@@ -94,6 +94,9 @@ enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
 #define RS_RUN_ASYNC     1u   /* return after enqueueing on the pipeline's HIP stream */
 #define RS_RUN_PER_STREAM 2u  /* one launch per stream instead of one batched launch */
 
+/* serve() flags (besides RS_RUN_PER_STREAM) */
+#define RS_SERVE_DEVICE_OUT 8u /* out[i] holds device arrays that the kernel writes directly */
+
 /* read_*() flags */
 #define RS_READ_BLOCK    0u
 #define RS_NONBLOCK      1u   /* RS_ENOTREADY instead of waiting */
@@ -287,12 +290,16 @@ typedef struct {
  * one of the pipeline's two launch lanes is free and the HBM budget allows (requests that
  * do not fit wait for earlier ones to finish and release their memory), reaps finished
  * batches without blocking, copies each request's aggregates into out[i] (host memory;
- * out may be NULL, or out[i] fields NULL) and releases it.  With RS_RUN_PER_STREAM every
+ * out may be NULL, or out[i] fields NULL) and releases it.  With RS_SERVE_DEVICE_OUT, out[i]
+ * instead holds device arrays of n_parents entries for every field of agg_fields (none NULL;
+ * owned by the caller, untouched by the library once serve returns); the kernel writes the
+ * aggregates there in place, so a finished request costs no copy, and the pipeline must not
+ * emit an output stream.  With RS_RUN_PER_STREAM every
  * request is launched alone, in arrival order, on one lane: the one-launch-per-stream
  * baseline.  Requests are sorted by arrival by the caller.  timing[i] receives the
  * request's clock.  Returns RS_OK when every request completed; a request that fails
  * records its error in timing[i].status and the loop goes on.
- * Errors: RS_EINVAL (NULL arguments, unsorted arrivals). */
+ * Errors: RS_EINVAL (NULL arguments, unsorted arrivals, a NULL device destination). */
 int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view *out, rs_request_timing *timing,
           uint32_t flags);
 

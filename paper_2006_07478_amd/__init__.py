@@ -21,6 +21,7 @@ RS_MODFILTER, RS_HASH_EXPAND, RS_TEXT_WORDS, RS_GRAPH_THRESH, RS_HASH_TREE = 1, 
 RS_COUNT, RS_SUM, RS_MIN, RS_MAX, RS_KEPT_COUNT, RS_KEPT_SUM = 1, 2, 4, 8, 16, 32
 RS_MEM_HOST, RS_MEM_DEVICE = 0, 1
 RS_RUN_SYNC, RS_RUN_ASYNC, RS_RUN_PER_STREAM = 0, 1, 2
+RS_SERVE_DEVICE_OUT = 8
 RS_READ_BLOCK, RS_NONBLOCK, RS_READ_DEVICE, RS_READ_RELEASE = 0, 1, 2, 4
 RS_COLLECT_STATS, RS_NO_GRAPH, RS_TIME_KERNEL = 1, 2, 4
 
@@ -316,10 +317,13 @@ class Pipeline:
         """Pipeline-kernel device times (ms) of the launches since the last call (RS_TIME_KERNEL)."""
         return kernel_times(self.h, cap)
 
-    def serve(self, requests, arrivals, per_stream=False, read=True):
+    def serve(self, requests, arrivals, per_stream=False, read=True, device_out=None):
         """Run the native serving loop over requests = [(offsets, elements[, lengths, parent_param])]
         arriving at the given times (seconds, sorted).  Returns (results, timings): results[i] is a
-        dict of aggregate arrays (or None when read is False) and timings a list of dicts."""
+        dict of aggregate arrays (or None when read is False) and timings a list of dicts.
+        device_out: a list of dicts of device tensors (one per stored field, n_parents entries
+        each, per request) that the kernel writes directly (RS_SERVE_DEVICE_OUT); results[i] is
+        then that dict."""
         n = len(requests)
         reqs = (rs_request * max(n, 1))()
         outs = (rs_agg_view * max(n, 1))()
@@ -333,7 +337,12 @@ class Pipeline:
             reqs[i].stream = s
             P = int(s.n_parents)
             res = None
-            if read:
+            if device_out is not None:
+                res = device_out[i]
+                for name, bit, dt in FIELDS:
+                    if self.desc.agg_fields & bit and res.get(name) is not None:
+                        setattr(outs[i], name, res[name].data_ptr())
+            elif read:
                 res = {}
                 for name, bit, dt in FIELDS:
                     if self.desc.agg_fields & bit:
@@ -341,7 +350,8 @@ class Pipeline:
                         res[name] = a
                         setattr(outs[i], name, a.ctypes.data)
             results.append((res, P))
-        serve(self.h, reqs, n, outs if read else None, tim, RS_RUN_PER_STREAM if per_stream else 0)
+        flags = (RS_RUN_PER_STREAM if per_stream else 0) | (RS_SERVE_DEVICE_OUT if device_out is not None else 0)
+        serve(self.h, reqs, n, outs if (read or device_out is not None) else None, tim, flags)
         out = [None if res is None else {k: a[:P] for k, a in res.items()} for res, P in results]
         timings = [dict(arrival=t.arrival_s, pushed=t.pushed_s, launched=t.launched_s, completed=t.completed_s,
                         batch=t.batch, status=t.status) for t in tim[:n]]

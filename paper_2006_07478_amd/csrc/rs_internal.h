@@ -10,6 +10,7 @@ namespace rs {
 enum Ctl : uint32_t {
     CTL_ERROR = 2,          // watchdog / protocol error flag (sticky until read)
     CTL_EPOCH = 3,          // launch epoch (look-back state tags)
+    CTL_BAD = 4,            // some stream of the batch has malformed regions (its ST_ERROR word says which)
     CTL_NPART = 64,         // claim partitions (8 per XCD); a launch uses 64, or 1 (the kernel relies on this)
     CTL_PART = 64,          // claim counter of partition q at CTL_PART + q * CTL_PART_STRIDE
     CTL_PART_STRIDE = 32,   // one 128-byte line per counter

@@ -740,6 +740,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 if (t == 0) {
                     __hip_atomic_fetch_or((GLOBAL unsigned int *)&sd.stats[ST_ERROR], 1u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_or(&ctl[CTL_BAD], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (a.emit_outputs)   // successors of this claim must not wait for it
                         __hip_atomic_store(&sd.lookback[cidx], ((unsigned long long)epoch_tag << 40) | (2ull << 38),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

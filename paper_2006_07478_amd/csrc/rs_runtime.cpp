@@ -185,6 +185,8 @@ struct Stream {
     uint64_t footprint = 0;
     uint64_t batch = 0;            // batch this stream runs in
     hipEvent_t ready = nullptr;    // its host-to-device copies have landed (pushes that do not wait)
+    rs_agg_view direct{};          // caller's device arrays the kernel writes directly (serve with RS_SERVE_DEVICE_OUT)
+    bool has_direct = false;
     ~Stream() {
         if (ready) (void)hipEventDestroy(ready);
     }
@@ -200,6 +202,8 @@ struct Batch {
     rs::LaunchArgs args{};
     hipStream_t lane = nullptr;
     uint64_t launches = 0;         // launches of this batch (its control block counts them too)
+    uint64_t checked = ~0ull;      // launch count at which err_word and bad_word were read
+    uint32_t err_word = 0, bad_word = 0;
     hipGraphExec_t graph = nullptr;
     hipEvent_t done = nullptr;
     ~Batch() {
@@ -384,12 +388,21 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
         e.offsets = s->offsets;
         e.lengths = s->lengths;
         e.pparam = s->pparam;
-        e.agg_count = (uint32_t *)s->count.p;
-        e.agg_sum = (unsigned long long *)s->sum.p;
-        e.agg_min = (uint32_t *)s->min.p;
-        e.agg_max = (uint32_t *)s->max.p;
-        e.agg_kcount = (uint32_t *)s->kcount.p;
-        e.agg_ksum = (unsigned long long *)s->ksum.p;
+        if (s->has_direct) {
+            e.agg_count = s->direct.count;
+            e.agg_sum = (unsigned long long *)s->direct.sum;
+            e.agg_min = s->direct.min;
+            e.agg_max = s->direct.max;
+            e.agg_kcount = s->direct.kept_count;
+            e.agg_ksum = (unsigned long long *)s->direct.kept_sum;
+        } else {
+            e.agg_count = (uint32_t *)s->count.p;
+            e.agg_sum = (unsigned long long *)s->sum.p;
+            e.agg_min = (uint32_t *)s->min.p;
+            e.agg_max = (uint32_t *)s->max.p;
+            e.agg_kcount = (uint32_t *)s->kcount.p;
+            e.agg_ksum = (unsigned long long *)s->ksum.p;
+        }
         e.stats = (unsigned long long *)s->stats.p;   // the error word is always written
         if (p->d.emit_outputs && !probe) {
             const size_t lb_bytes = 8ull * s->n_claims + 8;
@@ -512,10 +525,18 @@ int launch_batch(rs_pipeline *p, Batch &b, bool graph, bool timed = false) {
     return RS_OK;
 }
 
+// Reads the control block's error and malformed-region words once per finished launch (the
+// caller has waited for it); a batch's streams are then checked without a copy each.
 int batch_error(Batch &b) {
-    uint32_t err = 0;
-    HIP_OR(hipMemcpy(&err, (uint32_t *)b.ctl.p + rs::CTL_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
-    if (err) return fail(RS_EDEVICE, "the device scheduler stopped a claim (watchdog or internal check)");
+    if (b.checked != b.launches) {
+        uint32_t w[3] = {0, 0, 0};
+        static_assert(rs::CTL_BAD == rs::CTL_ERROR + 2, "control words read together");
+        HIP_OR(hipMemcpy(w, (uint32_t *)b.ctl.p + rs::CTL_ERROR, sizeof w, hipMemcpyDeviceToHost), RS_EDEVICE);
+        b.err_word = w[0];
+        b.bad_word = w[2];
+        b.checked = b.launches;
+    }
+    if (b.err_word) return fail(RS_EDEVICE, "the device scheduler stopped a claim (watchdog or internal check)");
     return RS_OK;
 }
 
@@ -617,7 +638,8 @@ int find_done(rs_pipeline *p, uint64_t id, uint32_t flags, Stream **out) {
     int rc = batch_error(b);
     if (rc) return rc;
     uint32_t bad = 0;
-    HIP_OR(hipMemcpy(&bad, (unsigned long long *)s->stats.p + rs::ST_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
+    if (b.bad_word)
+        HIP_OR(hipMemcpy(&bad, (unsigned long long *)s->stats.p + rs::ST_ERROR, 4, hipMemcpyDeviceToHost), RS_EDEVICE);
     if (bad) return fail(RS_EINVAL, "stream %llu has malformed regions (out of order or past n_elements)",
                          (unsigned long long)id);
     s->state = S_DONE;
@@ -708,7 +730,8 @@ RS_API int pipeline_set_stream(rs_pipeline *p, void *hip_stream) {
 }
 
 namespace {
-int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bool wait);
+int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bool wait,
+                const rs_agg_view *direct = nullptr);
 }
 
 RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id) {
@@ -717,8 +740,10 @@ RS_API int stream_push(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream
 
 namespace {
 // wait: return after the copies have landed, so the caller may reuse its host arrays; else the
-// stream's launch waits for them on the device (serve(), whose requests outlive the loop)
-int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bool wait) {
+// stream's launch waits for them on the device (serve(), whose requests outlive the loop).
+// direct: device arrays of the caller that receive the aggregates in place of the stream's own.
+int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bool wait,
+                const rs_agg_view *direct) {
     clear_error();
     if (!p || !stream_id) return fail(RS_EINVAL, "NULL argument");
     int rc = check_stream(p, s);
@@ -768,7 +793,7 @@ int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bo
     st->mean_len = P ? covered / (double)P : 0.0;
 
     // device footprint (look-back words at one per parent at most)
-    const uint64_t agg_bytes = P * ((p->d.agg_fields & RS_COUNT ? 4 : 0) + (p->d.agg_fields & RS_SUM ? 8 : 0) +
+    const uint64_t agg_bytes = direct ? 0 : P * ((p->d.agg_fields & RS_COUNT ? 4 : 0) + (p->d.agg_fields & RS_SUM ? 8 : 0) +
                                     (p->d.agg_fields & RS_MIN ? 4 : 0) + (p->d.agg_fields & RS_MAX ? 4 : 0) +
                                     (p->d.agg_fields & RS_KEPT_COUNT ? 4 : 0) + (p->d.agg_fields & RS_KEPT_SUM ? 8 : 0));
     uint64_t in_bytes = 0;
@@ -813,12 +838,17 @@ int push_stream(rs_pipeline *p, const rs_stream_desc *s, uint64_t *stream_id, bo
         st->pparam = s->parent_param;
         // borrowed regions are checked by the kernel, claim by claim, before any element is read
     }
-    if (p->d.agg_fields & RS_COUNT && (rc = st->count.alloc(4 * P))) return rc;
-    if (p->d.agg_fields & RS_SUM && (rc = st->sum.alloc(8 * P))) return rc;
-    if (p->d.agg_fields & RS_MIN && (rc = st->min.alloc(4 * P))) return rc;
-    if (p->d.agg_fields & RS_MAX && (rc = st->max.alloc(4 * P))) return rc;
-    if (p->d.agg_fields & RS_KEPT_COUNT && (rc = st->kcount.alloc(4 * P))) return rc;
-    if (p->d.agg_fields & RS_KEPT_SUM && (rc = st->ksum.alloc(8 * P))) return rc;
+    if (direct) {
+        st->direct = *direct;
+        st->has_direct = true;
+    } else {
+        if (p->d.agg_fields & RS_COUNT && (rc = st->count.alloc(4 * P))) return rc;
+        if (p->d.agg_fields & RS_SUM && (rc = st->sum.alloc(8 * P))) return rc;
+        if (p->d.agg_fields & RS_MIN && (rc = st->min.alloc(4 * P))) return rc;
+        if (p->d.agg_fields & RS_MAX && (rc = st->max.alloc(4 * P))) return rc;
+        if (p->d.agg_fields & RS_KEPT_COUNT && (rc = st->kcount.alloc(4 * P))) return rc;
+        if (p->d.agg_fields & RS_KEPT_SUM && (rc = st->ksum.alloc(8 * P))) return rc;
+    }
     if ((rc = st->stats.alloc(8 * rs::ST_WORDS))) return rc;
     HIP_OR(hipMemsetAsync(st->stats.p, 0, 8 * rs::ST_WORDS, hs), RS_EDEVICE);
     if (wait) {
@@ -1033,7 +1063,21 @@ RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view
                  uint32_t flags) {
     clear_error();
     if (!p || (n && (!reqs || !timing))) return fail(RS_EINVAL, "NULL argument");
-    if (flags & ~RS_RUN_PER_STREAM) return fail(RS_EINVAL, "unknown serve flags");
+    if (flags & ~(RS_RUN_PER_STREAM | RS_SERVE_DEVICE_OUT)) return fail(RS_EINVAL, "unknown serve flags");
+    const bool dev_out = flags & RS_SERVE_DEVICE_OUT;
+    if (dev_out) {
+        if (n && !out) return fail(RS_EINVAL, "RS_SERVE_DEVICE_OUT needs out");
+        if (p->d.emit_outputs) return fail(RS_EINVAL, "RS_SERVE_DEVICE_OUT: the pipeline emits an output stream");
+        for (uint64_t i = 0; i < n; ++i) {
+            const rs_agg_view &o = out[i];
+            const uint32_t f = p->d.agg_fields;
+            if (reqs[i].stream.n_parents &&
+                (((f & RS_COUNT) && !o.count) || ((f & RS_SUM) && !o.sum) || ((f & RS_MIN) && !o.min) ||
+                 ((f & RS_MAX) && !o.max) || ((f & RS_KEPT_COUNT) && !o.kept_count) ||
+                 ((f & RS_KEPT_SUM) && !o.kept_sum)))
+                return fail(RS_EINVAL, "request %llu: a destination of a stored field is NULL", (unsigned long long)i);
+        }
+    }
     for (uint64_t i = 1; i < n; ++i)
         if (reqs[i].arrival_s < reqs[i - 1].arrival_s) return fail(RS_EINVAL, "requests must be sorted by arrival");
     const bool per_stream = flags & RS_RUN_PER_STREAM;
@@ -1069,7 +1113,8 @@ RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view
         //    completions are not held up behind a long run of copies
         for (int pushed = 0; pushed < 4 && next < n && reqs[next].arrival_s <= now(); ++pushed) {
             uint64_t id = 0;
-            const int rc = push_stream(p, &reqs[next].stream, &id, false);   // the launch waits for the copy
+            // the launch waits for the copy on the device
+            const int rc = push_stream(p, &reqs[next].stream, &id, false, dev_out ? &out[next] : nullptr);
             if (rc) {
                 fail_req(next, rc);
             } else {
@@ -1119,8 +1164,9 @@ RS_API int serve(rs_pipeline *p, const rs_request *reqs, uint64_t n, rs_agg_view
         // 3. completions: reap finished batches without blocking
         for (size_t k = 0; k < inflight.size();) {
             const uint64_t i = inflight[k];
-            rs_agg_view dummy{nullptr, nullptr, nullptr, nullptr};
-            rs_agg_view *v = out ? &out[i] : &dummy;
+            rs_agg_view dummy{};
+            // device outputs are already in place: only the completion and the checks remain
+            rs_agg_view *v = (out && !dev_out) ? &out[i] : &dummy;
             const int rc = read_aggregates(p, sid[i], v, RS_NONBLOCK | RS_READ_RELEASE);
             if (rc == RS_ENOTREADY) {
                 ++k;

@@ -432,6 +432,20 @@ def test_malformed_device_regions_are_rejected():
                 with pytest.raises(rs.RsError) as ei:
                     p.read(sid)
                 assert ei.value.code == rs.RS_EINVAL
+    # one malformed stream among good ones in a batch: only it is refused
+    good = workloads.fixed_offsets(4096, 16)
+    ref = oracle.run(oracle.HASH_EXPAND, good, workloads.hash_values(1, 4096))
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256) as p:
+        g = torch.from_numpy(good.view(np.int32)).cuda()
+        ids = [p.push(g, vals, n_elements=4096),
+               p.push(torch.from_numpy(bad_offsets[0].view(np.int32)).cuda(), vals, n_elements=4096),
+               p.push(g, vals, n_elements=4096)]
+        p.run()
+        check(p.read(ids[0]), ref, where="good stream before the malformed one")
+        with pytest.raises(rs.RsError) as ei:
+            p.read(ids[1])
+        assert ei.value.code == rs.RS_EINVAL
+        check(p.read(ids[2]), ref, where="good stream after the malformed one")
     # text lines that overlap
     text = torch.from_numpy(np.frombuffer(b"ab cd\nef gh\n" + b" " * 4, np.uint8).copy()).cuda()
     with rs.Pipeline(rs.RS_TEXT_WORDS, strategy=rs.RS_TAG, ensemble_width=64) as p:
@@ -597,6 +611,40 @@ def test_serving_results_equal_alone_and_in_the_mix():
     for i in (0, 7, 31):
         got, _ = run_one(rs.RS_HASH_EXPAND, rs.RS_SIGNAL, 128, *reqs[i])
         check(got, refs[i], where=f"alone {i}")
+
+
+def test_serving_device_requests_into_device_outputs():
+    """RS_SERVE_DEVICE_OUT: device-resident requests whose aggregates the kernel writes straight
+    into the caller's device arrays equal the oracle, batched and one launch per request."""
+    import torch
+    say("serving device outputs")
+    n_req = 40
+    shapes_n, shapes_m = workloads.stream_shapes(seed=5, n_streams=n_req, lo_n=1e3, hi_n=2e5)
+    reqs = [workloads.serving_stream(5, s, int(shapes_n[s]), float(shapes_m[s])) for s in range(n_req)]
+    arrivals = np.sort(workloads.arrivals(6, n_req, 4000.0))
+    refs = [oracle.run(oracle.HASH_EXPAND, o, v) for o, v in reqs]
+    dev = [(torch.from_numpy(o.view(np.int32)).cuda(), torch.from_numpy(v.view(np.int32)).cuda()) for o, v in reqs]
+    tdt = {np.uint32: torch.int32, np.uint64: torch.int64}
+    for per_stream in (False, True):
+        outs = []
+        for o, v in reqs:
+            P = len(o) - 1
+            outs.append({name: torch.full((max(P, 1),), -1, dtype=tdt[dt], device="cuda")
+                         for name, bit, dt in rs.FIELDS if rs.DEFAULT_FIELDS[rs.RS_HASH_EXPAND] & bit})
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256) as p:
+            results, timings = p.serve(dev, arrivals, per_stream=per_stream, device_out=outs)
+        torch.cuda.synchronize()
+        for i in range(n_req):
+            assert timings[i]["status"] == 0
+            got = {k: t.cpu().numpy().view(dict(count=np.uint32, sum=np.uint64, min=np.uint32,
+                                                   max=np.uint32)[k]) for k, t in results[i].items()}
+            check(got, refs[i], where=f"device-out request {i} per_stream={per_stream}")
+    with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=rs.RS_TAG, ensemble_width=256) as p:
+        missing = [dict(outs[0])]
+        missing[0].pop("min")
+        with pytest.raises(rs.RsError) as ei:
+            p.serve(dev[:1], [0.0], device_out=missing)
+        assert ei.value.code == rs.RS_EINVAL
 
 
 def test_serving_rejects_a_request_larger_than_the_budget():
