@@ -3,12 +3,16 @@
 Workload: 2^26 hash-generated u32 elements in fixed-length regions, enumerated,
 filtered (bit 0 of H(x,0)), expanded into 0..3 children and aggregated per region
 (count, u64 sum, min, max).  A step is one pass of the whole path over the batch:
-one launch of the persistent pipeline kernel, replayed from a HIP graph, with the
-inputs already resident in HBM.  Three copies of the input rotate between steps so
-that the 256 MB last-level cache does not serve the reads.
+the reset kernel and one launch of the persistent pipeline kernel, with the inputs
+already resident in HBM.  The timed steps are direct launches (the pipelines are
+created with RS_TIME_KERNEL, which brackets every pipeline kernel with a HIP event
+pair and therefore launches directly instead of replaying a graph); the headline is
+also timed as graph replays of the same two kernels (`graph_replay`).  Three copies
+of the input rotate between steps so that the 256 MB last-level cache does not serve
+the reads.
 
 Prints one JSON line: the headline at L = 4096, the sweep over
-L in {1, 4, 16, 64, 256, 1024, 4096} for both strategies, the roofline of the
+L in {1, 4, 16, 64, 256, 1024, 4096} for every strategy, the roofline of the
 pipeline kernel, and the serial oracle timed on a bounded sample on the host.
 """
 import argparse
@@ -83,7 +87,8 @@ def time_config(rs, torch, stream, offsets, copies, strategy, width, steps, warm
         sid = p.push(offsets, vals, n_elements=N_ELEMENTS)   # device tensors: borrowed, already in HBM
         p.run()
         pipes.append((p, sid))
-    chosen = pipes[0][0].stats(pipes[0][1]).ensemble_width
+    st0 = pipes[0][0].stats(pipes[0][1])
+    chosen, qdepth = int(st0.ensemble_width), int(st0.queue_depth)
     for i in range(warmup):
         pipes[i % len(pipes)][0].run_again(rs.RS_RUN_ASYNC)
     torch.cuda.synchronize()
@@ -99,11 +104,36 @@ def time_config(rs, torch, stream, offsets, copies, strategy, width, steps, warm
     ms = e0.elapsed_time(e1) / steps
     kt = [t for p, _ in pipes for t in p.kernel_times()]
     assert len(kt) == steps, (len(kt), steps)
-    kernel_ms = {"mean": sum(kt) / len(kt), "median": float(np.median(kt)), "min": min(kt)}
+    kernel_ms = {"mean": sum(kt) / len(kt), "median": float(np.median(kt)), "min": min(kt), "queue_depth": qdepth}
     st = pipes[0][0].stats(pipes[0][1]) if stats else None
     for p, _ in pipes:
         p.close()
     return ms, kernel_ms, chosen, st
+
+
+def time_graph_replay(rs, torch, stream, offsets, copies, strategy, width, steps, warmup):
+    """The same steps as time_config, replayed from each pipeline's captured HIP graph (reset and
+    pipeline kernels): ms per step from events around all of them."""
+    pipes = []
+    for vals in copies:
+        p = rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=width)
+        p.set_stream(stream.cuda_stream)
+        p.push(offsets, vals, n_elements=N_ELEMENTS)
+        p.run()
+        pipes.append(p)
+    for i in range(warmup):
+        pipes[i % len(pipes)].run_again(rs.RS_RUN_ASYNC)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        pipes[i % len(pipes)].run_again(rs.RS_RUN_ASYNC)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    for p in pipes:
+        p.close()
+    return e0.elapsed_time(e1) / steps
 
 
 def occupancy_pass(rs, torch, stream, offsets, vals, strategy, width, L):
@@ -119,7 +149,7 @@ def occupancy_pass(rs, torch, stream, offsets, vals, strategy, width, L):
     full = lambda k: round(st.full[k] / max(1, st.firings[k]), 4)
     out = {"enum_occupancy": occ(0), "enum_full_frac": full(0), "expand_occupancy": occ(1),
            "agg_occupancy": occ(2), "agg_full_frac": full(2)}
-    if strategy == rs.RS_SIGNAL and L > 0:
+    if strategy in (rs.RS_SIGNAL, rs.RS_ENUM_TAG) and L > 0:
         out["enum_occupancy_closed_form"] = round(L / (width * -(-L // width)), 4)
     return out
 
@@ -139,17 +169,19 @@ def variable_sweep(rs, torch, stream, copies, steps, warmup, width=0):
         R = len(sizes)
         offsets = torch.from_numpy(offs_h.view(np.int32)).cuda()
         row = {"max": mx, "regions": R}
-        for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal"), (rs.RS_SIGNAL_LANES, "lanes")):
+        for s, name in ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal"), (rs.RS_SIGNAL_LANES, "lanes"),
+                        (rs.RS_ENUM_TAG, "enum+tag")):
             ms, kt, w, _ = time_config(rs, torch, stream, offsets, copies, s, width, steps, warmup)
             kms = kt["mean"]
             nbytes = 4 * N_ELEMENTS + 4 * (R + 1) + 20 * R
-            row[name] = {"ensemble_width": w, "ms": round(ms, 4), "kernel_ms": round(kms, 4),
+            row[name] = {"ensemble_width": w, "queue_depth": kt["queue_depth"], "ms": round(ms, 4),
+                         "kernel_ms": round(kms, 4),
                          "elements_per_s": N_ELEMENTS / (kms * 1e-3), "GB_per_s": round(nbytes / (kms * 1e-3) / 1e9, 1)}
             occ = occupancy_pass(rs, torch, stream, offsets, copies[0], s, w, 0)
             row[name]["enum_occupancy"] = occ["enum_occupancy"]
-            if s == rs.RS_SIGNAL:
+            if s in (rs.RS_SIGNAL, rs.RS_ENUM_TAG):
                 row[name]["enum_occupancy_closed_form"] = round(float(sizes.sum()) / (w * float(np.sum(-(-sizes // w)))), 4)
-            print(f"[bench] variable max={mx:5d} {name:6s} w={w:4d} kernel {kms:8.3f} ms  "
+            print(f"[bench] variable max={mx:5d} {name:8s} w={w:4d} kernel {kms:8.3f} ms  "
                   f"{N_ELEMENTS / (kms * 1e-3) / 1e9:7.2f} Gelem/s", file=sys.stderr, flush=True)
         rows.append(row)
     return rows
@@ -337,6 +369,8 @@ def other_configs(rs, torch, stream, steps=5):
         strats = ((rs.RS_TAG, "tag"), (rs.RS_SIGNAL, "signal"))
         if kind != rs.RS_TEXT_WORDS:
             strats += ((rs.RS_SIGNAL_LANES, "lanes"),)
+        if kind in (rs.RS_TEXT_WORDS, rs.RS_HASH_EXPAND, rs.RS_HASH_TREE):
+            strats += ((rs.RS_ENUM_TAG, "enum+tag"),)
         for s, name in strats:
             kw = {} if param is None else {"param": param}
             with rs.Pipeline(kind, strategy=s, ensemble_width=0, agg_fields=fields, flags=rs.RS_TIME_KERNEL,
@@ -345,7 +379,8 @@ def other_configs(rs, torch, stream, steps=5):
                 sid = p.push(offsets, elements, lengths=lengths, parent_param=parent_param,
                              n_elements=int(elements.numel()))
                 p.run()
-                w = int(p.stats(sid).ensemble_width)
+                st = p.stats(sid)
+                w, q = int(st.ensemble_width), int(st.queue_depth)
                 for _ in range(2):
                     p.run_again(rs.RS_RUN_ASYNC)
                 torch.cuda.synchronize()
@@ -355,7 +390,7 @@ def other_configs(rs, torch, stream, steps=5):
                 kt = p.kernel_times()
             ms = float(np.median(kt))
             n = int(elements.numel())
-            res[name] = {"ensemble_width": w, "kernel_ms_median": round(ms, 4),
+            res[name] = {"ensemble_width": w, "queue_depth": q, "kernel_ms_median": round(ms, 4),
                          "elements_per_s": n / (ms * 1e-3), "GB_per_s": round(n_bytes_alg / (ms * 1e-3) / 1e9, 1)}
         return res
 
@@ -391,6 +426,25 @@ def other_configs(rs, torch, stream, steps=5):
         rs.RS_TEXT_WORDS, dev(starts), dev(text), len(text) + 8 * R + 8 * R, lengths=dev(lengths),
         fields=rs.RS_COUNT | rs.RS_MAX)}
     del text, starts, lengths
+    # the taxi-shaped text (long lines of mean 1397 bytes, few spaces): the three versions of the
+    # paper's taxi comparison are signals, enumeration then tags, and tags
+    text, starts, lengths = workloads.taxi_workload(seed=9, total_bytes=1 << 30)
+    R = len(starts)
+    out["taxi_text_1GiB"] = {"n_elements": len(text), "n_parents": R, **kernel_rate(
+        rs.RS_TEXT_WORDS, dev(starts), dev(text), len(text) + 8 * R + 8 * R, lengths=dev(lengths),
+        fields=rs.RS_COUNT | rs.RS_MAX)}
+    del text, starts, lengths
+    # tree topology: the filter feeds the expansion and a second aggregating node (kept count
+    # and sum) at the headline size, regions of 16 and 4096
+    vals = workloads.hash_values(2, N_ELEMENTS)
+    dv = dev(vals)
+    for L in (16, 4096):
+        offsets = workloads.fixed_offsets(N_ELEMENTS, L)
+        R = len(offsets) - 1
+        out[f"tree_2p26_L{L}"] = {"n_elements": N_ELEMENTS, "n_parents": R, **kernel_rate(
+            rs.RS_HASH_TREE, dev(offsets), dv, 4 * N_ELEMENTS + 4 * (R + 1) + 32 * R,
+            fields=rs.DEFAULT_FIELDS[rs.RS_HASH_TREE])}
+    del vals, dv
     # C4: 2^24 vertices, 2^28 edges
     offsets, w, thr, _ = workloads.graph_workload(seed=4)
     R = len(offsets) - 1
@@ -479,11 +533,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--width", type=int, default=0, help="ensemble width; 0 lets the autotuner choose")
+    ap.add_argument("--width", default="0",
+                    help="ensemble width (0 lets the autotuner choose), or one per strategy as tag:128,signal:64")
     ap.add_argument("--headline-only", action="store_true", help="time only L = 4096 (for profiling)")
+    ap.add_argument("--lengths", default="",
+                    help="comma-separated region lengths to time instead of the whole sweep (for profiling); "
+                         "prints the sweep rows only unless 4096 is among them")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing of the headline")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="time only the other workloads (C1, C3, taxi-shaped text, tree, C4), for profiling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--strategy", choices=["tag", "signal", "lanes", "both", "all"], default="all",
-                    help="lanes: the lane-resolved signals the paper proposes as future work")
+    ap.add_argument("--strategy", choices=["tag", "signal", "lanes", "enum_tag", "both", "all"], default="all",
+                    help="lanes: the lane-resolved signals the paper proposes as future work; enum_tag: "
+                         "enumeration in the first stage, tags after it")
     ap.add_argument("--no-occupancy", action="store_true", help="skip the per-node statistics pass of the sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the 512-stream batching/serving leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1/C3/C4 workloads")
@@ -501,6 +563,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.configs_only:
+        print(json.dumps({"configs": other_configs(rs, torch, stream)}))
+        return
     t_gen = time.perf_counter()
     # three resident copies (seeds 2, 102, 202); the first is the seed-2 workload
     copies = [torch.from_numpy(workloads.hash_values(2 + 100 * c, N_ELEMENTS).view(np.int32)).cuda()
@@ -508,33 +573,51 @@ def main():
     print(f"[bench] generated {COPIES} x 2^26 elements in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
           flush=True)
     strategies = {"tag": [rs.RS_TAG], "signal": [rs.RS_SIGNAL], "lanes": [rs.RS_SIGNAL_LANES],
-                  "both": [rs.RS_TAG, rs.RS_SIGNAL],
-                  "all": [rs.RS_TAG, rs.RS_SIGNAL, rs.RS_SIGNAL_LANES]}[args.strategy]
-    names = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal", rs.RS_SIGNAL_LANES: "lanes"}
+                  "enum_tag": [rs.RS_ENUM_TAG], "both": [rs.RS_TAG, rs.RS_SIGNAL],
+                  "all": [rs.RS_TAG, rs.RS_SIGNAL, rs.RS_SIGNAL_LANES, rs.RS_ENUM_TAG]}[args.strategy]
+    names = {rs.RS_TAG: "tag", rs.RS_SIGNAL: "signal", rs.RS_SIGNAL_LANES: "lanes", rs.RS_ENUM_TAG: "enum+tag"}
     lengths = [HEADLINE_L] if args.headline_only else LENGTHS
+    partial = bool(args.lengths)
+    if partial:
+        lengths = [int(x) for x in args.lengths.split(",")]
+    if ":" in args.width:
+        wmap = {k.strip(): int(v) for k, v in (kv.split(":") for kv in args.width.split(","))}
+        width_of = lambda s: wmap.get(names[s].replace("+", "_"), 0)
+    else:
+        width_of = lambda s: int(args.width)
     sweep = []
     head = {}
     for L in lengths:
         offsets = torch.from_numpy(workloads.fixed_offsets(N_ELEMENTS, L).view(np.int32)).cuda()
         row = {"L": L}
         for s in strategies:
-            ms, kt, w, _ = time_config(rs, torch, stream, offsets, copies, s, args.width, args.steps,
+            ms, kt, w, _ = time_config(rs, torch, stream, offsets, copies, s, width_of(s), args.steps,
                                        args.warmup)
             kms = kt["mean"]
             eps = N_ELEMENTS / (ms * 1e-3)
             gbs = algorithmic_bytes(N_ELEMENTS, L) / (ms * 1e-3) / 1e9
             row[names[s]] = {"ms": round(ms, 4), "kernel_ms": round(kms, 4), "elements_per_s": eps,
-                             "GB_per_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "ensemble_width": w}
-            if not args.no_occupancy and not args.headline_only:   # headline-only: the profiled command
+                             "GB_per_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "ensemble_width": w,
+                             "queue_depth": kt["queue_depth"]}
+            if not args.no_occupancy and not args.headline_only and not partial:   # the profiled commands
                 row[names[s]].update(occupancy_pass(rs, torch, stream, offsets, copies[0], s, w, L))
-            print(f"[bench] L={L:5d} {names[s]:6s} w={w:4d} {ms:8.3f} ms  {eps / 1e9:7.2f} Gelem/s  {gbs:7.1f} GB/s",
+            print(f"[bench] L={L:5d} {names[s]:8s} w={w:4d} {ms:8.3f} ms  {eps / 1e9:7.2f} Gelem/s  {gbs:7.1f} GB/s",
                   file=sys.stderr, flush=True)
             if L == HEADLINE_L:
                 head[names[s]] = (ms, eps, gbs, w, kt)
         sweep.append(row)
 
+    if partial and not head:
+        print(json.dumps({"sweep": sweep, "n_elements": N_ELEMENTS, "steps": args.steps, "warmup": args.warmup}))
+        return
     best = max(head, key=lambda k: head[k][1])
     ms, eps, gbs, w_best, kt_best = head[best]
+    best_s = {v: k for k, v in names.items()}[best]
+    graph_ms = None
+    if not args.no_graph:
+        offsets = torch.from_numpy(workloads.fixed_offsets(N_ELEMENTS, HEADLINE_L).view(np.int32)).cuda()
+        graph_ms = time_graph_replay(rs, torch, stream, offsets, copies, best_s, w_best, args.steps, args.warmup)
+        print(f"[bench] L={HEADLINE_L} {best} graph replays {graph_ms:.4f} ms per step", file=sys.stderr, flush=True)
     kms = kt_best["mean"]
     # roofline of the dominant kernel: algorithmic bytes over its own mean launch duration
     kgbs = algorithmic_bytes(N_ELEMENTS, HEADLINE_L) / (kms * 1e-3) / 1e9
@@ -556,7 +639,12 @@ def main():
         "config": {"workload": "boundary-frequency sweep: 2^26 hash-generated u32, fixed region length, "
                                "filter -> expand 0..3 -> per-region u64 sum/min/max/count",
                    "n_elements": N_ELEMENTS, "region_length": HEADLINE_L, "strategy": best,
-                   "ensemble_width": w_best, "input_copies_rotated": COPIES},
+                   "ensemble_width": w_best, "queue_depth": kt_best["queue_depth"],
+                   "input_copies_rotated": COPIES,
+                   "timed_launches": "direct (reset + pipeline kernel, event pair around each pipeline kernel)"},
+        "graph_replay": None if graph_ms is None else {
+            "ms_per_step": round(graph_ms, 4), "elements_per_s": N_ELEMENTS / (graph_ms * 1e-3),
+            "note": "the same steps replayed from the captured HIP graph of reset + pipeline kernel"},
         "roofline": {"bound": "hbm", "achieved": round(kgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel_ms": round(kms, 4),
                      "kernel_ms_median": round(kt_best["median"], 4), "kernel_ms_min": round(kt_best["min"], 4),
@@ -565,9 +653,11 @@ def main():
         "hbm_probe": probe,
         "sweep": sweep,
     }
+    if partial:
+        args.no_variable = args.no_configs = args.no_serving = True
     if not args.headline_only and not args.no_variable:
         line["variable_sweep"] = variable_sweep(rs, torch, stream, copies, args.steps, args.warmup, args.width)
-    if not args.headline_only:
+    if not args.headline_only and not partial:
         line["output_stream"] = output_stream_rate(rs, torch, stream, copies[0], HEADLINE_L)
         print(f"[bench] output stream: {json.dumps(line['output_stream'])}", file=sys.stderr, flush=True)
     if not args.headline_only and not args.no_configs:

@@ -252,14 +252,19 @@ int length_bucket(double mean_len) { return (int)std::lround(2.0 * std::log2(std
 
 bool depth_ok(uint32_t width, uint32_t q) { return q && !(q & (q - 1)) && q >= 2 * width && q <= 8 * width; }
 
-bool cache_lookup(uint32_t kind, uint32_t emit, int bucket, uint32_t *strategy, uint32_t *width, uint32_t *depth) {
+// The last cached choice for (kind, emit, bucket) that agrees with what the pipeline fixed itself
+// (want_*: a strategy, width or depth, or RS_AUTO / 0 for free), so that pipelines of different
+// fixed strategies keep their own tuned choices side by side.
+bool cache_lookup(uint32_t kind, uint32_t emit, int bucket, uint32_t want_s, uint32_t want_w, uint32_t want_q,
+                  uint32_t *strategy, uint32_t *width, uint32_t *depth) {
     FILE *f = fopen(cache_path().c_str(), "r");
     if (!f) return false;
     unsigned k, e, s, w, q;
     int b;
     bool found = false;
     while (fscanf(f, "%u %u %d %u %u %u", &k, &e, &b, &s, &w, &q) == 6) {
-        if (k == kind && e == emit && b == bucket && s != RS_AUTO && rs::kernel_supported(k, s, w) && depth_ok(w, q)) {
+        if (k == kind && e == emit && b == bucket && s != RS_AUTO && rs::kernel_supported(k, s, w) && depth_ok(w, q) &&
+            (want_s == RS_AUTO || want_s == s) && (want_w == 0 || want_w == w) && (want_q == 0 || want_q == q)) {
             *strategy = s;
             *width = w;
             *depth = q;
@@ -560,8 +565,7 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
     const int bucket = length_bucket(parents > 0 ? covered / parents : 0.0) + (sel.size() > 1 ? 1000 : 0);
     const uint32_t want_s = p->d.strategy, want_w = p->d.ensemble_width, want_q = p->d.queue_depth;
     uint32_t cs = 0, cw = 0, cq = 0;
-    if (cache_lookup(p->d.kind, p->d.emit_outputs, bucket, &cs, &cw, &cq) && (want_s == RS_AUTO || want_s == cs) &&
-        (want_w == 0 || want_w == cw) && (want_q == 0 || want_q == cq)) {
+    if (cache_lookup(p->d.kind, p->d.emit_outputs, bucket, want_s, want_w, want_q, &cs, &cw, &cq)) {
         p->strategy = cs;
         p->width = cw;
         p->qdepth = cq;

@@ -487,8 +487,20 @@ def test_autotuned_pipeline_matches_oracle(tmp_path, monkeypatch):
                 assert st.ensemble_width in WIDTHS
                 assert st.strategy in strats(rs.RS_HASH_EXPAND, st.ensemble_width)
                 assert st.queue_depth in (2 * st.ensemble_width, 4 * st.ensemble_width)
-    lines = (tmp_path / "tune.txt").read_text().split("\n")
-    assert len([l for l in lines if l.strip()]) == 2
+    n_lines = lambda: len([l for l in (tmp_path / "tune.txt").read_text().split("\n") if l.strip()])
+    assert n_lines() == 2
+    # pipelines that fix different strategies keep their own cached choices side by side: the
+    # second round tunes nothing
+    counts = []
+    for _ in range(2):
+        for s in (rs.RS_SIGNAL, rs.RS_TAG):
+            with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=s, ensemble_width=0, flags=rs.RS_COLLECT_STATS) as p:
+                sid = p.push(offsets, vals)
+                p.run()
+                check(p.read(sid), ref, where=f"fixed strategy {s}, tuned width")
+                assert p.stats(sid).strategy == s
+        counts.append(n_lines())
+    assert counts[0] <= 4 and counts[1] == counts[0]
 
 
 # ---- every configuration the autotuner can pick ----
