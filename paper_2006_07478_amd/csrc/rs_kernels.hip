@@ -5,7 +5,9 @@
 // under a non-preemptive scheduler whose state is wave-uniform and lives in scalar
 // registers.  It takes parent batches ("claims") from its partition of the launch's
 // claims (eight partitions per XCD): most by index, the rest from the partition's
-// counter, then from other partitions, returning only when every claim is done.
+// counter, then from other partitions, returning only when every claim is done.  Under an
+// ordered output stream every claim comes from one ascending counter instead (see the
+// claim code: the look-back's progress must not depend on which waves are resident).
 // A firing consumes an ensemble of at most w = 64*V items: item i sits on lane
 // i mod 64 in round i / 64, so one firing is V rounds of 64-lane SIMD work.
 //
@@ -23,7 +25,22 @@
 //     regions freely, and the aggregating node reduces by tag (§5); or
 //   - as lane-resolved signals (RS_SIGNAL_LANES, the future work of §6): the signals and
 //     their queues of RS_SIGNAL, but ensembles may span them, and every node computes each
-//     lane's region from the pending signals' positions instead of storing it.
+//     lane's region from the pending signals' positions instead of storing it; or
+//   - per stage (RS_ENUM_TAG, the mixed version of §5's taxi comparison): the enumerating
+//     node caps every ensemble at its region's end as under signals, and what it emits
+//     downstream carries tags.
+// The tree kind (RS_HASH_TREE, §2.1's tree topologies) gives the filter node two consumers:
+// the expansion and a second aggregating node of its own, whose per-region count and sum
+// are kept beside the first sink's records.
+//
+// An ensemble that is full and inside one region runs its filter and expansion as one
+// firing (hash kinds, every strategy): the children go straight into the aggregating
+// node's queue and that node takes whole 64-lane rounds, so the scheduler pass and the
+// first queue's LDS round trip are paid once per ensemble.  The run of such firings ends
+// at the first ensemble that is not full or spans a region end.
+//
+// Queue depths are launch parameters (a power of two in [2w, 8w]), placed in dynamic LDS
+// with the claim's region table and aggregate slots.
 // Aggregates are exact integer reductions kept in LDS slots per claim and written once
 // per parent; a claim always holds whole regions, so no aggregate is ever shared
 // between waves.  How an ensemble reaches the slots depends on the regions it spans: one
@@ -33,10 +50,12 @@
 // first, so one lane per block adds to the slot.
 //
 // Elements reach the enumerating node from HBM through direct buffer->LDS loads into a
-// one-ensemble staging slot; the next firing's ensemble is requested as soon as the
-// current one is taken, so the loads overlap the downstream firings, and their
-// completion is awaited explicitly.  The next claim's region table is loaded into
-// registers while the current claim runs.
+// one-ensemble staging slot (16 bytes per lane per load for full ensembles of four or more
+// items per lane); the next firing's ensemble is requested as soon as the current one is
+// taken, so the loads overlap the downstream firings, and their completion is awaited
+// explicitly.  Text is staged the same way, byte windows per firing.  The next claim's
+// region table is loaded into registers while the current claim runs, and its first
+// ensemble is requested as the current claim ends.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
