@@ -512,7 +512,10 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
     // text: a firing's bytes from the word before its first address, in 1, 1, 2, 4 or 8 copies of
     // 256 bytes (at least w + 8 bytes)
     constexpr uint32_t TB = V <= 2 ? 256u : 2u * EW;
-    __shared__ uint32_t fsl[BYTES ? TB / 4u : EW];   // staging slot for the enumerating node's next ensemble
+    // text under tags: two windows of TWB bytes, alternating (a window holds TWB / w firings: four,
+    // or sixteen at w = 64; measured best among 1, 2 and 4 KB at w = 256 and 512)
+    constexpr uint32_t TWB = EW < 256u ? 1024u : 4u * EW;
+    __shared__ uint32_t fsl[BYTES ? (TAG ? 2u * TWB / 4u : TB / 4u) : EW];   // staging for the enumerating node
     extern __shared__ __attribute__((aligned(16))) uint8_t dyn[];
 
     const Dyn lay = dyn_layout(KIND, STRAT, EW, D1, a.bmax);
@@ -806,6 +809,22 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                                         false);
             }
         };
+        // Text under tags: the claim's bytes from tr_f0 on, in windows of TWB bytes (window m in
+        // buffer m mod 2).  A firing never straddles two windows (w divides TWB and firings start
+        // at tr_f0 + k w); the first firing of window m waits for it, keeps the last word of window
+        // m - 1 (the byte before its first), and requests window m + 1 into the buffer m - 1 held,
+        // so a window's copy overlaps the TWB / w firings of the window before it.
+        uint32_t tr_f0 = 0, tr_m = 0xFFFFFFFFu, tr_carry = 0x20202020u;
+        auto tring_request = [&](uint32_t m) {
+            if constexpr (BYTES && TAG) {
+                const uint32_t wb = tr_f0 + m * TWB;
+                if (wb < vend) {
+                    const uint32_t nbytes = min(TWB, sd.n_elements - wb);
+                    lds_copy<TWB / 256u>(rsrc_words(elems + wb, nbytes), uni(lds_addr(fsl + (m & 1u) * (TWB / 4u))), t,
+                                         nbytes == TWB);
+                }
+            }
+        };
         // u32 elements outside the staged path (the output-count pass): plain buffer loads
         auto load_ens = [&](uint32_t pos, uint32_t n, uint32_t (&x)[V]) {
             const __amdgpu_buffer_rsrc_t r = rsrc(elems + (size_t)pos * 4u, n * 4u);
@@ -896,7 +915,6 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 return in_line && cb != 32u && prev == 32u;
             }
         };
-
         bool failed = false;
         bool out_ok = true;   // the claim's output base is known (ordered output stream)
         // ---- ordered output stream: count this claim's outputs, then learn its base from the
@@ -995,7 +1013,8 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         uint32_t sq1 = 0, sq2 = 0;                          // signal queues (entry n in lane n mod 64)
         // enumerating node: signal strategy walks region fj at position fpos;
         // tag strategy walks ensembles of EW consecutive positions from fpos.
-        uint32_t fj = 0, fpos = vbeg, jlo = 0;
+        // (text under tags starts at the word boundary below: its firings take aligned words)
+        uint32_t fj = 0, fpos = (BYTES && TAG) ? (vbeg & ~3u) : vbeg, jlo = 0;
         uint32_t rend = 0, ls = 0, lv = 0;                  // current region's end, line address, line position
         // tag strategy: start of region jlo + 1 (every position below it lies in region jlo or before)
         uint32_t jnext = 0xFFFFFFFFu;
@@ -1036,6 +1055,11 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         uint32_t iters = 0;
 
         if (spos != fpos) stage(fpos);
+        if constexpr (BYTES && TAG) {
+            tr_f0 = fpos;
+            tr_m = 0xFFFFFFFFu;
+            tring_request(0u);
+        }
 
         // tree: the second sink's per-lane accumulators (the filter's survivors) and their region
         uint32_t k2c = 0, k2r = 0;
@@ -1375,16 +1399,94 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // ---------------- F: the enumerating node, one firing of e items from fpos
         // nbound (lane-resolved signals): the ends of regions jb .. jb + nbound - 1 fall in this
         // ensemble or at its end, and their signals go out with it
+        // Text under tags, four bytes per lane.  The firing's ensemble [fpos, fpos + e) starts at
+        // a multiple of 4 on this path; lane t of round k takes the aligned word at
+        // a = fpos + 4 (64 k + t) from the staged window and flags its bytes four at a time: a byte
+        // starts a word when it lies in a line, is not a space, and follows a space or is its
+        // line's first byte.  A word holds at most two starts (each follows a space or a line
+        // start), queued with their lines' tags in address order.  The lines that meet the
+        // ensemble are those from jlo on that start at or before its last byte: lane q reads line
+        // jlo + q's start and end once, and every lane then walks them as uniform values (no
+        // chain of LDS round trips).  jlo becomes the last of them.  Returns how many it queued.
+        auto text_starts4 = [&](uint32_t e) -> uint32_t {
+            constexpr uint32_t NW = EW / 4u, RW = (NW + 63u) / 64u;
+            const uint32_t last = fpos + e - 1u;
+            uint32_t inl[RW], lst[RW], rof[RW];
+#pragma unroll
+            for (uint32_t k = 0; k < RW; ++k) inl[k] = lst[k] = rof[k] = 0u;
+            for (uint32_t jb0 = jlo;;) {
+                const uint32_t jq = jb0 + t;
+                const bool have = jq < nb;
+                const uint32_t cs = have ? SX[jq] : 0xFFFFFFFFu;
+                const uint32_t ce = have ? cs + (VT[jq + 1u] - VT[jq]) : 0u;
+                const uint32_t nd = (uint32_t)__popcll(__ballot(have && cs <= last));   // a prefix of the lanes
+                for (uint32_t d = 0; d < nd; ++d) {
+                    const uint32_t st = __builtin_amdgcn_readlane(cs, d), en = __builtin_amdgcn_readlane(ce, d);
+#pragma unroll
+                    for (uint32_t k = 0; k < RW; ++k) {
+                        const uint32_t a = fpos + 4u * (k * 64u + t);
+                        const uint32_t sb = st - a;   // the line's first byte in this word when below 4
+                        const uint32_t lo = st > a ? min(sb, 4u) : 0u;
+                        const uint32_t hi = en > a ? min(en - a, 4u) : 0u;
+                        // bytes lo .. hi - 1 of the word lie in line jb0 + d
+                        const uint32_t m = hi > lo ? (0x80808080u >> (8u * (4u - hi))) & (0x80808080u << (8u * lo)) : 0u;
+                        inl[k] |= m;
+                        rof[k] |= (m >> 7) * (jb0 + d);
+                        lst[k] |= (sb < 4u && m != 0u) ? 0x80u << (8u * sb) : 0u;
+                    }
+                }
+                if (nd < 64u) {
+                    if (nd) jlo = jb0 + nd - 1u;
+                    break;
+                }
+                jb0 += 64u;
+            }
+            uint32_t run = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < RW; ++k) {
+                const uint32_t i = k * 64u + t;
+                const uint32_t a = fpos + 4u * i;
+                const uint32_t nin = (i < NW && 4u * i < e) ? min(4u, e - 4u * i) : 0u;   // bytes of the ensemble
+                const uint32_t ens = nin >= 4u ? 0x80808080u : 0x80808080u & ((1u << (8u * nin)) - 1u);
+                const uint32_t off = a - (tr_f0 + tr_m * TWB);   // the word's byte offset in its window
+                const uint32_t wi = (tr_m & 1u) * (TWB / 4u) + (nin ? off >> 2 : 1u);
+                const uint32_t cur = fsl[wi];
+                const uint32_t prv = (nin && off == 0u) ? tr_carry : fsl[wi - 1u];
+                const uint32_t sp = space_bytes(cur);
+                const uint32_t after_sp = (sp << 8) | (space_bytes(prv) >> 24);
+                const uint32_t starts = ~sp & (after_sp | lst[k]) & inl[k] & ens;
+                const uint32_t c = (uint32_t)__builtin_popcount(starts);   // 0, 1 or 2
+                const uint32_t f0 = starts ? (uint32_t)__builtin_ctz(starts) >> 3 : 0u;
+                const uint32_t s1 = starts & (starts - 1u);
+                const uint32_t f1 = s1 ? (uint32_t)__builtin_ctz(s1) >> 3 : 0u;
+                const uint64_t b1 = __ballot(c & 1u), b2 = __ballot(c & 2u);
+                const uint32_t within = rank_below(b1) + 2u * rank_below(b2);
+                const uint32_t pc = (uint32_t)__popcll(b1) + 2u * (uint32_t)__popcll(b2);
+                const uint32_t spill = D1 + ((t1 + run + pc + t - within) & 63u);
+                const uint32_t p0 = pick(__ballot(c != 0u), (t1 + run + within) & (D1 - 1u), spill);
+                const uint32_t p1 = pick(b2, (t1 + run + within + 1u) & (D1 - 1u), spill);
+                q1v[p0] = a + f0;
+                q1t[p0] = (uint8_t)(rof[k] >> (8u * f0));
+                q1v[p1] = a + f1;
+                q1t[p1] = (uint8_t)(rof[k] >> (8u * f1));
+                run += pc;
+            }
+            return run;
+        };
         auto f_node = [&](auto full, uint32_t e, uint32_t nbound) {
             constexpr bool FULL = decltype(full)::value;
             // the items' own regions: for tags, and for lane-resolved signals of a kind that reads
             // the parent's context
             constexpr bool FREG = TAG || (LANES && (CTXP || TREE));
+            constexpr bool SWAR = BYTES && TAG;   // text under tags: four bytes per lane
             bool one = true;
             if constexpr (FREG) one = jnext > fpos + e - 1u;
             uint32_t reg[V], x[V];
             uint64_t kb[V];   // kept-item masks per round (lane-resolved signals)
-            if constexpr (FREG) {
+            if constexpr (SWAR) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) reg[k] = 0;
+            } else if constexpr (FREG) {
                 f_regions(full, fpos, e, jlo, one, reg);
             } else {
 #pragma unroll
@@ -1395,6 +1497,15 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 wait_vmem<0>();   // the slot's copy has landed
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = fsl[k * 64 + t];
+            } else if constexpr (SWAR) {
+                const uint32_t m = (fpos - tr_f0) / TWB;
+                if (m != tr_m) {
+                    wait_vmem<0>();   // window m has landed
+                    // the word before window m, read before its buffer is refilled
+                    tr_carry = m ? uni(fsl[((m - 1u) & 1u) * (TWB / 4u) + TWB / 4u - 1u]) : 0x20202020u;
+                    tr_m = m;
+                    tring_request(m + 1u);
+                }
             } else {
                 const uint32_t adr0 = TAG ? fpos : ls + (fpos - lv);   // the firing's first byte
                 if (tspos != adr0) stage_text(adr0);
@@ -1404,8 +1515,9 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             const uint32_t thr = (CTXP && !WALK) ? uni(CX[fj]) : 0u;
             uint32_t run = 0;
+            if constexpr (SWAR) run = text_starts4(e);   // also moves jlo to the last line it met
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
+            for (int k = 0; k < (SWAR ? 0 : V); ++k) {
                 const uint32_t i = (uint32_t)k * 64u + t;
                 uint32_t item, aux;
                 const bool keep = f_item(BoolC<true>{}, i, FULL || i < e, fpos, x[k], reg[k], thr, ls, lv, item, aux);
@@ -1422,10 +1534,12 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             if constexpr (FREG) {
                 if (!one) {
-                    const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
+                    if constexpr (!SWAR) {
+                        const uint32_t kl = (e - 1u) >> 6, ll = (e - 1u) & 63u;
 #pragma unroll
-                    for (int k = 0; k < V; ++k)
-                        if ((uint32_t)k == kl) jlo = __builtin_amdgcn_readlane(reg[k], ll);
+                        for (int k = 0; k < V; ++k)
+                            if ((uint32_t)k == kl) jlo = __builtin_amdgcn_readlane(reg[k], ll);
+                    }
                     jnext = jlo + 1u < nb ? uni((BYTES ? SX : VT)[jlo + 1u]) : 0xFFFFFFFFu;
                 }
             }
@@ -1451,7 +1565,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 const uint32_t nf = fpos + e;
                 uint32_t nadr = 0xFFFFFFFFu;
                 if constexpr (TAG) {
-                    if (nf < vend) nadr = nf;
+                    (void)nf;   // the window ring requests ahead by itself
                 } else {
                     if (nf < rend) nadr = ls + (nf - lv);
                     else if (fj + 1u < nb) nadr = uni(SX[fj + 1u]);
