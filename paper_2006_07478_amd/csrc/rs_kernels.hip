@@ -852,25 +852,30 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             if (one_) {
 #pragma unroll
                 for (int k = 0; k < V; ++k) reg[k] = jlo_;
-            } else if (jlo_ + 8u >= nb || uni(key[jlo_ + 8u]) > last) {
-                // at most eight region starts inside the ensemble: one uniform pass over them,
-                // each lane counting the starts at or before its item (equal starts, i.e. empty
-                // regions, all count)
-#pragma unroll
-                for (int k = 0; k < V; ++k) reg[k] = jlo_;
-                for (uint32_t j = jlo_ + 1u; j < nb; ++j) {
-                    const uint32_t st = uni(key[j]);
-                    if (st > last) break;
-#pragma unroll
-                    for (int k = 0; k < V; ++k) reg[k] += fpos_ + (uint32_t)k * 64u + t >= st ? 1u : 0u;
-                }
             } else {
-                // many short regions: a binary search per lane
+                // the next eight region starts, read at once (lane q: start jlo_ + 1 + q)
+                const uint32_t jq = jlo_ + 1u + t;
+                const uint32_t ks = (t < 8u && jq < nb) ? key[jq] : 0xFFFFFFFFu;
+                if (__builtin_amdgcn_readlane(ks, 7) > last) {
+                    // at most seven of them inside the ensemble: a uniform pass over them, each
+                    // lane counting the starts at or before its item (equal starts, i.e. empty
+                    // regions, all count)
 #pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const uint32_t i = (uint32_t)k * 64u + t;
-                    jlo_ = f_region(fpos_ + (FULL || i < e ? i : 0u), jlo_);   // positions grow with k
-                    reg[k] = jlo_;
+                    for (int k = 0; k < V; ++k) reg[k] = jlo_;
+                    const uint32_t nin = (uint32_t)__popcll(__ballot(ks <= last));   // a prefix of the lanes
+                    for (uint32_t q = 0; q < nin; ++q) {
+                        const uint32_t st = __builtin_amdgcn_readlane(ks, q);
+#pragma unroll
+                        for (int k = 0; k < V; ++k) reg[k] += fpos_ + (uint32_t)k * 64u + t >= st ? 1u : 0u;
+                    }
+                } else {
+                    // many short regions: a binary search per lane
+#pragma unroll
+                    for (int k = 0; k < V; ++k) {
+                        const uint32_t i = (uint32_t)k * 64u + t;
+                        jlo_ = f_region(fpos_ + (FULL || i < e ? i : 0u), jlo_);   // positions grow with k
+                        reg[k] = jlo_;
+                    }
                 }
             }
         };
@@ -1497,6 +1502,10 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 wait_vmem<0>();   // the slot's copy has landed
 #pragma unroll
                 for (int k = 0; k < V; ++k) x[k] = fsl[k * 64 + t];
+                // the slot's words are in registers: request the next firing's ensemble now, so that
+                // its copy overlaps this firing too
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                stage(fpos + e);
             } else if constexpr (SWAR) {
                 const uint32_t m = (fpos - tr_f0) / TWB;
                 if (m != tr_m) {
@@ -1558,7 +1567,7 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
                 }
             }
             if constexpr (!BYTES) {
-                stage(fpos + e);   // the slot's contents are in registers
+                // requested above, once the slot's words were in registers
             } else {
                 // the next firing's window: the rest of this line, else the next line (tags: the next
                 // address); a wrong guess is staged again when that firing starts
