@@ -656,7 +656,8 @@ def main():
     if partial:
         args.no_variable = args.no_configs = args.no_serving = True
     if not args.headline_only and not args.no_variable:
-        line["variable_sweep"] = variable_sweep(rs, torch, stream, copies, args.steps, args.warmup, args.width)
+        line["variable_sweep"] = variable_sweep(rs, torch, stream, copies, args.steps, args.warmup,
+                                                0 if ":" in args.width else int(args.width))
     if not args.headline_only and not partial:
         line["output_stream"] = output_stream_rate(rs, torch, stream, copies[0], HEADLINE_L)
         print(f"[bench] output stream: {json.dumps(line['output_stream'])}", file=sys.stderr, flush=True)
