@@ -68,6 +68,21 @@ def measured_traffic(strategy, width):
     return None
 
 
+def parse_widths(arg):
+    """--width: one ensemble width for every strategy ("256"; 0 lets the autotuner choose) or one
+    per strategy ("tag:128,signal:64,lanes:64,enum_tag:128").  Returns {strategy name: width}."""
+    names = ("tag", "signal", "lanes", "enum_tag")
+    if ":" not in arg:
+        return {n: int(arg) for n in names}
+    out = {n: 0 for n in names}
+    for kv in arg.split(","):
+        k, v = kv.split(":")
+        if k.strip() not in out:
+            raise ValueError(f"unknown strategy {k!r} in --width")
+        out[k.strip()] = int(v)
+    return out
+
+
 def algorithmic_bytes(n, L):
     """Bytes the path must move per run: elements, CSR offsets, 20 B of aggregates per region."""
     R = (n + L - 1) // L
@@ -580,11 +595,7 @@ def main():
     partial = bool(args.lengths)
     if partial:
         lengths = [int(x) for x in args.lengths.split(",")]
-    if ":" in args.width:
-        wmap = {k.strip(): int(v) for k, v in (kv.split(":") for kv in args.width.split(","))}
-        width_of = lambda s: wmap.get(names[s].replace("+", "_"), 0)
-    else:
-        width_of = lambda s: int(args.width)
+    width_of = lambda s: parse_widths(args.width).get(names[s].replace("+", "_"), 0)
     sweep = []
     head = {}
     for L in lengths:
@@ -657,7 +668,8 @@ def main():
         args.no_variable = args.no_configs = args.no_serving = True
     if not args.headline_only and not args.no_variable:
         line["variable_sweep"] = variable_sweep(rs, torch, stream, copies, args.steps, args.warmup,
-                                                0 if ":" in args.width else int(args.width))
+                                                parse_widths(args.width).get("tag", 0)
+                                                if ":" not in args.width else 0)
     if not args.headline_only and not partial:
         line["output_stream"] = output_stream_rate(rs, torch, stream, copies[0], HEADLINE_L)
         print(f"[bench] output stream: {json.dumps(line['output_stream'])}", file=sys.stderr, flush=True)

@@ -47,3 +47,13 @@ def test_measured_traffic_needs_a_matching_entry(tmp_path, monkeypatch):
     assert bench.measured_traffic("tag", 256) == 123
     assert bench.measured_traffic("tag", 128) is None
     assert bench.measured_traffic("signal", 256) is None   # taken on other device code
+
+
+def test_width_argument_forms():
+    assert bench.parse_widths("0") == {"tag": 0, "signal": 0, "lanes": 0, "enum_tag": 0}
+    assert bench.parse_widths("256")["enum_tag"] == 256
+    w = bench.parse_widths("tag:128,signal:64,enum_tag:128")
+    assert w == {"tag": 128, "signal": 64, "lanes": 0, "enum_tag": 128}
+    import pytest
+    with pytest.raises(ValueError):
+        bench.parse_widths("tags:128")
