@@ -85,6 +85,17 @@ __device__ __forceinline__ constexpr uint32_t salt_key(uint32_t s) { return 0x9E
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Sum of a 64-bit value over the wave's 64 lanes (every lane receives it).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, 64);
+        v += ((unsigned long long)hi << 32) | lo;
+    }
+    return v;
+}
+
 __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -964,45 +975,60 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
             }
             // look-back: words are (epoch tag << 40) | (flag << 38) | value, flag 1 = this claim's
             // own count, flag 2 = inclusive prefix through this claim, flag 3 = no valid prefix
-            // (a predecessor's look-back gave up).  Each wait on a predecessor is bounded in real
-            // time (s_memrealtime counts at 100 MHz): past the bound the claim publishes flag 3,
-            // writes no outputs and raises the launch's error flag, so every wave still finishes
-            // and the host reports a device error instead of waiting for ever.
+            // (a predecessor's look-back gave up).  The whole wave looks back 64 claims per step:
+            // lane q reads claim base - 1 - q, and the step ends at the nearest claim holding flag
+            // 2 or 3, summing the counts before it (a wave reduction).  A step waits while any claim
+            // it needs has published nothing; each wait is bounded in real time (s_memrealtime
+            // counts at 100 MHz): past the bound the claim publishes flag 3, writes no outputs and
+            // raises the launch's error flag, so every wave still finishes and the host reports a
+            // device error instead of waiting for ever.
             unsigned long long prefix = 0;
             uint32_t lb_ok = 1;
-            if (t == 0) {
+            {
                 GLOBAL unsigned long long *lb = sd.lookback;
                 const unsigned long long tagw = (unsigned long long)epoch_tag << 40;
                 const unsigned long long mask38 = (1ull << 38) - 1ull;
                 const unsigned long long limit = 100ull * a.lb_wait_us;
-                __hip_atomic_store(&lb[cidx], tagw | (1ull << 38) | (n_out & mask38), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                for (uint32_t i = cidx; i-- > 0;) {
-                    unsigned long long w = 0;
-                    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-                    for (;;) {
-                        w = __hip_atomic_load(&lb[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if ((w >> 40) == (unsigned long long)epoch_tag && ((w >> 38) & 3ull)) break;
+                if (t == 0)
+                    __hip_atomic_store(&lb[cidx], tagw | (1ull << 38) | (n_out & mask38), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t base = cidx;   // the claims before base are still to be accounted for
+                unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+                while (base > 0u) {
+                    const bool valid = t < base;
+                    const unsigned long long w =
+                        valid ? __hip_atomic_load(&lb[base - 1u - t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+                    const uint32_t fl = (valid && (w >> 40) == (unsigned long long)epoch_tag) ? (uint32_t)(w >> 38) & 3u : 0u;
+                    const uint64_t stop = __ballot(fl >= 2u);
+                    // lanes [0, need) take part: up to the nearest flag 2 or 3, else every valid lane
+                    const uint32_t need = stop ? (uint32_t)__builtin_ctzll(stop) + 1u : min(base, 64u);
+                    const uint64_t needm = need >= 64u ? ~0ull : (1ull << need) - 1ull;
+                    if (__ballot(fl == 0u) & needm) {   // a claim it needs has published nothing yet
                         if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
-                            w = 3ull << 38;
+                            lb_ok = 0;
                             break;
                         }
                         __builtin_amdgcn_s_sleep(2);
+                        continue;
                     }
-                    if (((w >> 38) & 3ull) == 3ull) {
+                    if (stop && __builtin_amdgcn_readlane(fl, need - 1u) == 3u) {
                         lb_ok = 0;
                         break;
                     }
-                    prefix += w & mask38;
-                    if (((w >> 38) & 3ull) == 2ull) break;
+                    prefix += wave_sum_u64(t < need ? (w & mask38) : 0ull);
+                    if (stop) break;
+                    base = base > 64u ? base - 64u : 0u;
+                    t0 = __builtin_amdgcn_s_memrealtime();
                 }
                 // the outputs must fit the stream's output array (k_max items per element)
                 const unsigned long long cap = (unsigned long long)sd.n_elements * KE;
                 if (prefix + n_out > cap) lb_ok = 0;
-                __hip_atomic_store(&lb[cidx],
-                                   lb_ok ? tagw | (2ull << 38) | ((prefix + n_out) & mask38) : tagw | (3ull << 38),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (!lb_ok) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (t == 0) {
+                    __hip_atomic_store(&lb[cidx],
+                                       lb_ok ? tagw | (2ull << 38) | ((prefix + n_out) & mask38) : tagw | (3ull << 38),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (!lb_ok) __hip_atomic_fetch_or(&ctl[CTL_ERROR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
             out_rank = ((unsigned long long)uni((uint32_t)(prefix >> 32)) << 32) | uni((uint32_t)prefix);
             lb_ok = uni(lb_ok);
