@@ -232,16 +232,28 @@ def test_batched_streams_equal_alone():
 
 
 def test_run_again_replays_bit_exact():
-    offsets = workloads.fixed_offsets(1 << 20, 64)
-    vals = workloads.hash_values(2, 1 << 20)
+    """Replays equal the oracle, and every replay processes every element: a replay that skipped
+    claims would leave the earlier launch's (equal) aggregates in place, so the statistics, which
+    accumulate over launches, count the first node's items per launch as well."""
+    n = 1 << 20
+    offsets = workloads.fixed_offsets(n, 64)
+    vals = workloads.hash_values(2, n)
     ref = oracle.run(oracle.HASH_EXPAND, offsets, vals)
     for strategy in ALL3:
-        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256) as p:   # graph replays
             sid = p.push(offsets, vals)
             p.run()
             for _ in range(4):
                 p.run_again()
                 check(p.read(sid), ref, where="replay")
+        with rs.Pipeline(rs.RS_HASH_EXPAND, strategy=strategy, ensemble_width=256, flags=rs.RS_COLLECT_STATS) as p:
+            sid = p.push(offsets, vals)
+            p.run()
+            assert p.stats(sid).items[0] == n
+            for i in range(4):
+                p.run_again()
+                check(p.read(sid), ref, where="replay")
+                assert p.stats(sid).items[0] == (i + 2) * n, f"replay {i}: claims skipped"
 
 
 def test_signal_occupancy_matches_closed_form():
