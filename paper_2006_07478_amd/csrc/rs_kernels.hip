@@ -1133,10 +1133,12 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         auto flush_wave = [&](uint32_t j) {
             const Acc r = wave_reduce(acc);
             if (t == 0 && r.cnt) {
-                atomicAdd(&s_cnt[j], r.cnt);
-                atomicAdd(&s_sum[j], r.sum);
-                atomicMin(&s_min[j], r.mn);
-                atomicMax(&s_max[j], r.mx);
+                // one lane of the wave that owns this LDS: a plain read-modify-write (the wave's
+                // LDS accesses take effect in program order, after any lane's atomics before it)
+                s_cnt[j] += r.cnt;
+                s_sum[j] += r.sum;
+                s_min[j] = min(s_min[j], r.mn);
+                s_max[j] = max(s_max[j], r.mx);
             }
             acc_reset(acc);
         };
@@ -1759,6 +1761,16 @@ __global__ void __launch_bounds__(64) rs_pipeline(LaunchArgs a) {
         // lane-resolved signals the region ends before fpos then count as signalled and taken).
         // Returns whether the ensemble is full and inside that region.
         auto fuse_walk_region = [&](uint32_t &lt) -> bool {
+            // still inside the region A holds, as the cached start of the next region shows: no
+            // region table read (the common case of a run inside a long region)
+            if constexpr (LANES) {
+                if (utag == jb && jb < nb && fpos + EW <= bnext) {
+                    ja = jb;
+                    return true;
+                }
+            } else {
+                if (utag == jlo && fpos + EW <= jnext) return true;
+            }
             const uint32_t r = region_of(fpos, TAG ? jlo : jb);
             if (r != utag) {
                 fuse_drain(lt);
