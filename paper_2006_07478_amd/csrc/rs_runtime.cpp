@@ -382,10 +382,22 @@ int make_batch(rs_pipeline *p, const std::vector<Stream *> &sel, uint64_t batch_
     for (size_t i = 0; i < sel.size(); ++i) {
         Stream *s = sel[i];
         uint32_t P = s->n_parents;
-        // probe on a prefix of about 2^25 elements: enough claims to fill every compute unit,
-        // so the timing ranks configurations as the full stream would
-        if (probe && s->n_elements > (1u << 25) && P > 1)
+        // probe on a prefix of about 2^25 elements, so the timing ranks configurations as the
+        // full stream would.  A lone stream's prefix also holds claims for two per wave at 32
+        // waves per compute unit under the widest candidate's claim plan (so every candidate
+        // times the same prefix): with fewer the probe leaves compute units idle and hides what
+        // larger queues and ensembles cost in resident waves (long regions, e.g. long text lines,
+        // give few claims per 2^25 elements)
+        if (probe && s->n_elements > (1u << 25) && P > 1) {
+            const uint32_t P0 = P;
             P = (uint32_t)std::max<uint64_t>(1, (uint64_t)((double)P * (double)(1u << 25) / s->n_elements));
+            if (sel.size() == 1) {
+                uint32_t B = 1, nc = 0;
+                claim_plan(p->d.kind, false, kWidths[sizeof kWidths / sizeof kWidths[0] - 1], P, s->mean_len, &B, &nc);
+                const uint64_t want = 64ull * (uint64_t)std::max(1, p->n_cu);
+                if (nc < want) P = (uint32_t)std::min<uint64_t>(P0, (uint64_t)P * want / std::max<uint32_t>(1, nc) + 1);
+            }
+        }
         plan_claims(s, p->d.kind, p->d.emit_outputs && !probe, p->width, P);
         rs::StreamDev &e = h[i];
         std::memset(&e, 0, sizeof e);
@@ -548,7 +560,8 @@ int batch_error(Batch &b) {
 // Time every candidate configuration on a probe batch that stands for the selection and keep the
 // fastest.  One launch runs one configuration for all of its streams, so the probe is the
 // selection itself, or, above about 2^25 elements, every k-th stream of it in push order (each
-// stream probed on a prefix of at most 2^25 elements): a mix of short- and long-region streams
+// stream probed on a prefix of about 2^25 elements, a lone stream's prefix lengthened until it
+// fills the grid with claims): a mix of short- and long-region streams
 // is tuned as a mix.  The cache key is the probe's mean region length, kept apart for mixes.
 int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
     constexpr uint64_t kProbeElems = 1ull << 25;
