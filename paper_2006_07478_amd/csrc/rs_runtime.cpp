@@ -558,7 +558,7 @@ int batch_error(Batch &b) {
 }
 
 // Time every candidate configuration on a probe batch that stands for the selection and keep the
-// fastest.  One launch runs one configuration for all of its streams, so the probe is the
+// fastest (a runner-up within 5% is timed again beside it, and the second timing decides).  One launch runs one configuration for all of its streams, so the probe is the
 // selection itself, or, above about 2^25 elements, every k-th stream of it in push order (each
 // stream probed on a prefix of about 2^25 elements, a lone stream's prefix lengthened until it
 // fills the grid with claims): a mix of short- and long-region streams
@@ -584,12 +584,40 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
         p->qdepth = cq;
         return RS_OK;
     }
-    float best = 1e30f;
-    uint32_t best_s = want_s == RS_AUTO ? RS_TAG : want_s, best_w = want_w ? want_w : 256;
-    uint32_t best_q = want_q ? want_q : 2 * best_w;
+    struct Cand {
+        uint32_t s, w, q;
+        float ms;
+    };
+    Cand c1{want_s == RS_AUTO ? (uint32_t)RS_TAG : want_s, want_w ? want_w : 256u, 0u, 1e30f};
+    c1.q = want_q ? want_q : 2 * c1.w;
+    Cand c2 = c1;   // the fastest and the runner-up
     hipEvent_t e0, e1;
     HIP_OR(hipEventCreate(&e0), RS_EDEVICE);
     HIP_OR(hipEventCreate(&e1), RS_EDEVICE);
+    // one configuration on the probe: a warm-up, then the fastest of reps timed launches (one slow
+    // launch, from another process or a clock change, does not decide the pick)
+    auto time_cfg = [&](uint32_t strat, uint32_t w, uint32_t q, int reps, float *out) -> int {
+        p->strategy = strat;
+        p->width = w;
+        p->qdepth = q;
+        std::unique_ptr<Batch> b;
+        int r = make_batch(p, probe, 0, true, b);
+        if (r) return r;
+        if ((r = launch_batch(p, *b, false))) return r;
+        float ms = 1e30f;
+        for (int i = 0; i < reps; ++i) {
+            if (hipEventRecord(e0, b->lane) != hipSuccess) return fail(RS_EDEVICE, "event record");
+            if ((r = launch_batch(p, *b, false))) return r;
+            if (hipEventRecord(e1, b->lane) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return fail(RS_EDEVICE, "event synchronize");
+            float one = 0;
+            (void)hipEventElapsedTime(&one, e0, e1);
+            ms = std::min(ms, one);
+        }
+        if ((r = batch_error(*b))) return r;
+        *out = ms;
+        return RS_OK;
+    };
     int rc = RS_OK;
     for (uint32_t strat : {(uint32_t)RS_TAG, (uint32_t)RS_SIGNAL, (uint32_t)RS_SIGNAL_LANES, (uint32_t)RS_ENUM_TAG}) {
         if (rc != RS_OK) break;
@@ -603,39 +631,27 @@ int autotune(rs_pipeline *p, const std::vector<Stream *> &sel) {
             const uint32_t q = want_q ? want_q : (wq % 2 ? 4 * w : 2 * w);
             // the queues and a full claim's arrays must fit a compute unit's LDS
             if (rs::blocks_per_cu(p->d.kind, strat, w, q, rs::claim_parents_max(w)) <= 0) continue;
-            p->strategy = strat;
-            p->width = w;
-            p->qdepth = q;
-            std::unique_ptr<Batch> b;
-            if ((rc = make_batch(p, probe, 0, true, b))) break;
-            if ((rc = launch_batch(p, *b, false))) break;   // warm-up
-            // the fastest of three timed launches: one slow launch (another process, a clock
-            // change) does not decide the pick
             float ms = 1e30f;
-            for (int r = 0; r < 3 && rc == RS_OK; ++r) {
-                if (hipEventRecord(e0, b->lane) != hipSuccess) { rc = fail(RS_EDEVICE, "event record"); break; }
-                if ((rc = launch_batch(p, *b, false))) break;
-                if (hipEventRecord(e1, b->lane) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = fail(RS_EDEVICE, "event synchronize");
-                    break;
-                }
-                float one = 0;
-                (void)hipEventElapsedTime(&one, e0, e1);
-                ms = std::min(ms, one);
-            }
-            if (rc) break;
-            if ((rc = batch_error(*b))) break;
-            if (ms < best) {
-                best = ms;
-                best_s = strat;
-                best_w = w;
-                best_q = q;
+            if ((rc = time_cfg(strat, w, q, 3, &ms))) break;
+            if (ms < c1.ms) {
+                c2 = c1;
+                c1 = Cand{strat, w, q, ms};
+            } else if (ms < c2.ms) {
+                c2 = Cand{strat, w, q, ms};
             }
         }
+    }
+    // a close call (runner-up within 5%) is timed again, six launches each, and decided on that
+    if (rc == RS_OK && c1.ms < 1e30f && c2.ms < 1.05f * c1.ms) {
+        float m1 = 1e30f, m2 = 1e30f;
+        if ((rc = time_cfg(c1.s, c1.w, c1.q, 6, &m1)) == RS_OK && (rc = time_cfg(c2.s, c2.w, c2.q, 6, &m2)) == RS_OK &&
+            m2 < m1)
+            c1 = c2;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    const uint32_t best_s = c1.s, best_w = c1.w, best_q = c1.q;
     p->strategy = best_s;
     p->width = best_w;
     p->qdepth = best_q;
