@@ -59,7 +59,7 @@ enum rs_status {
  * RS_ENUM_TAG: a choice per stage, the second version of the paper's taxi application (§5): the
  * enumerating stage works one region at a time, as under signals, and tags every item it emits
  * with that region, so the later stages work as under tags, their ensembles spanning regions.
- * Offered for the kinds with a second stage (RS_HASH_EXPAND, RS_TEXT_WORDS).  The autotuner
+ * Offered for the kinds with a second stage (RS_HASH_EXPAND, RS_HASH_TREE, RS_TEXT_WORDS).  The autotuner
  * therefore chooses per stage among signals on both edges (RS_SIGNAL), enumeration then tags
  * (RS_ENUM_TAG) and tags on both (RS_TAG), besides lane-resolved signals. */
 enum rs_strategy { RS_TAG = 0, RS_SIGNAL = 1, RS_AUTO = 2, RS_SIGNAL_LANES = 3, RS_ENUM_TAG = 4 };
