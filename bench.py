@@ -568,7 +568,7 @@ def main():
     ap.add_argument("--no-variable", action="store_true", help="skip the variable-size sweep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
+        print(f"bench.py measures one GPU: the library runs on a single MI355X and has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 

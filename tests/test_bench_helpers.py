@@ -57,3 +57,15 @@ def test_width_argument_forms():
     import pytest
     with pytest.raises(ValueError):
         bench.parse_widths("tags:128")
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one GPU: --gpus N above 1 exits with status 2 and says so, before it
+    touches a GPU."""
+    import os
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.abspath(bench.__file__), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and "--gpus 2" in r.stderr
