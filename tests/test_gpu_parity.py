@@ -866,3 +866,26 @@ def test_tree_output_stream_and_batch(strategy):
         p.run()
         for i, (o, v) in zip(ids, ins):
             check(p.read(i), oracle.run(oracle.HASH_TREE, o, v), TREE_FIELDS, "tree batch")
+
+
+# ---- fused runs across region boundaries near multiples of w ----
+
+@pytest.mark.parametrize("strategy", [rs.RS_TAG, rs.RS_SIGNAL, rs.RS_SIGNAL_LANES, rs.RS_ENUM_TAG])
+@pytest.mark.parametrize("kind", [rs.RS_HASH_EXPAND, rs.RS_HASH_TREE])
+def test_fused_runs_around_region_boundaries(kind, strategy):
+    """Region lengths just below, at and above multiples of w = 256 (and empty, single-element and
+    long regions) in a seeded order: fused runs start, cross region ends and stop at every kind of
+    boundary, including the cached next-region bound that lets a run under tags skip the region
+    table."""
+    say("fused boundaries", kind, SNAME[strategy])
+    rng = np.random.default_rng(11)
+    menu = np.array([0, 1, 3, 255, 256, 257, 511, 512, 513, 768, 1024, 1280, 4096, 5000], np.int64)
+    sizes = rng.choice(menu, size=1500)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    vals = workloads.hash_values(5, int(offsets[-1]))
+    oc = oracle.HASH_TREE if kind == rs.RS_HASH_TREE else oracle.HASH_EXPAND
+    ref = oracle.run(oc, offsets, vals)
+    fields = rs.DEFAULT_FIELDS[kind]
+    got, _ = run_one(kind, strategy, 256, offsets, vals, fields=fields)
+    check(got, ref, TREE_FIELDS if kind == rs.RS_HASH_TREE else ("count", "sum", "min", "max"),
+          f"fused boundaries {kind} {SNAME[strategy]}")
